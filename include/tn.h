@@ -1,0 +1,192 @@
+/*
+ * libtn: execution of a fixed tensor-network contraction tree on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The problem statement follows Sec. 2 of Gray & Kourtis, "Hyper-optimized
+ * tensor network contraction" (arXiv:2002.01935): leaf tensors T_v with
+ * ordered index tuples t_v over indices e of dimension |D(e)|, an optional
+ * list of open output indices, and a rooted binary contraction tree given by
+ * the child tuples l(v), r(v) with the leaves numbered first.  Each internal
+ * node is a pairwise contraction (Sec. 2): the product of its two children,
+ * summed over the indices that no longer occur outside its subtree.  Sliced
+ * indices (Sec. 4.7.1) are summed last, as an exterior sum over independent
+ * copies of the network, each with the sliced indices fixed.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: TN_OK (0) or a negative tn_status; tn_last_error() gives
+ *     a thread-local message.  No exception or abort crosses this ABI.
+ *   - Complex data is interleaved (re, im): complex64 = 2 x float,
+ *     complex128 = 2 x double.  Leaves are dense, row-major in t_v order
+ *     (last index fastest).  Outputs are row-major in out_idx order.
+ *   - Device pointers: leaves, outputs, gradients and the workspace live in
+ *     device memory owned by the caller.  Index lists, the tree, slice ids and
+ *     the pointer arrays themselves are host memory owned by the caller and
+ *     are not retained after the call returns (the plan copies what it needs).
+ *   - The library allocates no device memory.  The only device-side objects
+ *     it owns are HIP graphs cached inside a plan.  All work is enqueued on
+ *     the caller's stream (a hipStream_t passed as void*; NULL = default
+ *     stream); calls return without waiting for the GPU.
+ *   - One plan may be used by several threads only with distinct workspaces.
+ *     Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TN_OK = 0,
+    TN_E_INVALID = -1,     /* malformed network, tree, ids or null pointer */
+    TN_E_UNSUPPORTED = -2, /* valid input the GPU path does not run (non power-of-two dim, rank > 64) */
+    TN_E_DEVICE = -3,      /* a HIP call failed */
+    TN_E_WORKSPACE = -4    /* workspace missing or smaller than required */
+} tn_status;
+
+/* Arithmetic of the contraction.  C64 modes store complex64 tensors; the
+   pairwise products on matrix cores use:
+     TN_C64_4M     four real products per complex product, FP32 MFMA, FP32 accumulation
+     TN_C64_3M     three real products (Gauss/Karatsuba), FP32 MFMA, FP32 accumulation
+     TN_C64_BF16X3 4M with each FP32 operand split into bf16 hi + lo parts and the
+                   product formed as hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation
+     TN_C128       complex128 storage and FP64 arithmetic throughout
+   Small (non-matrix) contractions run on the vector ALU in the storage precision.
+   Slice sums and norm checks are always FP64. */
+typedef enum {
+    TN_C64_4M = 0,
+    TN_C64_3M = 1,
+    TN_C64_BF16X3 = 2,
+    TN_C128 = 3
+} tn_precision;
+
+typedef struct {
+    int32_t prec;                /* tn_precision */
+    int32_t autotune;            /* nonzero: tn_plan_tune may retune tile shapes */
+    int32_t max_inflight_slices; /* slices contracted together per launch; 0 = choose from workspace_cap */
+    int32_t reserved;
+    uint64_t workspace_cap;      /* bytes; 0 = no cap (in-flight slices default to 1) */
+} tn_options;
+
+typedef struct tn_plan_s* tn_plan_t;
+
+/*
+ * Compile a plan for one network structure and tree (Sec. 2; slicing Sec. 4.7.1).
+ *
+ * n_leaves          number of leaf tensors |V| (>= 1)
+ * rank[v]           number of axes of leaf v (d_v)
+ * leaf_idx          concatenation of the tuples t_v (index ids in [0, n_idx))
+ * idx_dim[e]        |D(e)|; the GPU path needs powers of two (else TN_E_UNSUPPORTED)
+ * n_out, out_idx    open output indices, in output axis order (may be 0 / NULL)
+ * left, right       n_leaves - 1 child pairs; internal node n_leaves + k has
+ *                   children left[k], right[k], each an earlier node id; every
+ *                   node except the last is used exactly once (a full binary tree)
+ * n_sliced, sliced_idx  indices summed last; slice id -> index values is mixed
+ *                   radix over this list, first index most significant
+ * opt               options (NULL = defaults: TN_C64_4M, no autotune)
+ * plan              receives the opaque plan
+ *
+ * Index e is kept at node v iff it occurs on a leaf below v and it is an open
+ * output or occurs on a leaf outside the subtree of v; with plain two-ended
+ * edges this is the symmetric-difference rule of eq. (incidence).
+ *
+ * Errors (TN_E_INVALID): null pointers; an index repeated within one leaf (a
+ * self-loop); a non-output index on only one leaf; a tree that is not a full
+ * binary tree over all leaves; a sliced index that is also an output, or
+ * listed twice; an output listed twice.  Host-only: enqueues no GPU work.
+ */
+int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* leaf_idx,
+            int32_t n_idx, const int64_t* idx_dim,
+            int32_t n_out, const int64_t* out_idx,
+            const int32_t* left, const int32_t* right,
+            int32_t n_sliced, const int64_t* sliced_idx,
+            const tn_options* opt, tn_plan_t* plan);
+
+/*
+ * Plan summary (any pointer may be NULL):
+ *   W        contraction width of the unsliced tree, log2 of the largest tensor (eq. edgecon)
+ *   W_s      width with the sliced indices removed
+ *   log2_C   log2 of the unsliced cost C (eq. vertexcon, internal nodes)
+ *   flops_8C_per_slice  8 * C of one slice: complex FLOPs as counted in Sec. 2
+ *   d_sliced number of slices, prod over sliced indices of |D(e)|
+ *   workspace_bytes  device workspace needed by tn_contract / tn_contract_sliced
+ */
+int tn_plan_info(tn_plan_t plan, int32_t* W, int32_t* W_s, double* log2_C,
+                 double* flops_8C_per_slice, int64_t* d_sliced, uint64_t* workspace_bytes);
+
+/* Device workspace needed by tn_contract_backward for the leaves wrt_leaf[0..n_wrt),
+   and the FLOPs (8C convention) of one slice of the backward pass including the
+   forward pass and recomputation.  Builds (and caches in the plan) the reverse
+   program for that leaf set; host-only. */
+int tn_plan_backward_info(tn_plan_t plan, int32_t n_wrt, const int32_t* wrt_leaf,
+                          uint64_t* workspace_bytes, double* flops_per_slice);
+
+/* Number of internal nodes, and per-node details for reporting: kernel class
+   (0 = vector ALU row kernel, 1 = vector ALU split-K, 2 = matrix-core GEMM),
+   log2 of the batch (H), free-left (M), free-right (N) and summed (K) sizes,
+   complex FLOPs (8 * 2^{H+M+N+K}) and algorithmic bytes (operands read once,
+   output written once) per slice. */
+int tn_plan_num_nodes(tn_plan_t plan, int32_t* n);
+int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t* logH,
+                      int32_t* logM, int32_t* logN, int32_t* logK, double* flops, double* bytes);
+
+/*
+ * Optional autotune pass: times the candidate tile shapes of every distinct
+ * matrix-core contraction shape on synthetic data in `workspace` and keeps the
+ * fastest in the plan.  Overwrites the workspace; synchronises the stream.
+ */
+int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void* stream);
+
+/*
+ * Contract an unsliced plan (n_sliced == 0).
+ * leaves[v]   device pointer to leaf v (complex64, or complex128 for TN_C128)
+ * out         device pointer, output in the plan's storage type, out_idx order
+ *             (one element for a scalar)
+ */
+int tn_contract(tn_plan_t plan, const void* const* leaves, void* out,
+                void* workspace, uint64_t workspace_bytes, void* stream);
+
+/*
+ * Sliced contraction (Sec. 4.7.1): the sum over the given slice ids of the
+ * contraction with the sliced indices fixed to each id's values.
+ * n_ids, slice_ids  host array of ids in [0, d_sliced); NULL = every id in
+ *                   ascending order.  Ids are summed in the order given.
+ * out_c128          device pointer, complex128, out_idx order; overwritten with
+ *                   the FP64 sum (each slice's root is promoted to FP64 and added
+ *                   in a fixed order, so repeated calls are bitwise identical)
+ * An unsliced plan is accepted (d_sliced = 1, id 0).
+ */
+int tn_contract_sliced(tn_plan_t plan, const void* const* leaves, int64_t n_ids,
+                       const int64_t* slice_ids, void* out_c128,
+                       void* workspace, uint64_t workspace_bytes, void* stream);
+
+/*
+ * Reverse mode.  grad_out_c128 (device, complex128, out_idx order) is
+ * dL/d conj(R) for the contraction value R summed over the given slice ids.
+ * For each requested leaf t = wrt_leaf[i], grads[i] (device, the leaf's storage
+ * type and shape) is overwritten with
+ *   grads[i][k] = sum_o conj(dR_o / dT_t[k]) * grad_out[o],
+ * PyTorch's convention for complex gradients.  The pass recomputes forward
+ * intermediates from checkpoints instead of storing every node value; the
+ * cotangent of a child is the parent's cotangent contracted with the complex
+ * conjugate of its sibling.  Each leaf may be listed once.
+ */
+int tn_contract_backward(tn_plan_t plan, const void* const* leaves,
+                         const void* grad_out_c128, int32_t n_wrt,
+                         const int32_t* wrt_leaf, void* const* grads,
+                         int64_t n_ids, const int64_t* slice_ids,
+                         void* workspace, uint64_t workspace_bytes, void* stream);
+
+void tn_plan_destroy(tn_plan_t plan);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

@@ -242,7 +242,7 @@ static int onet_build(onet* g, int32_t n_leaves, const int32_t* rank, const int6
                       const int32_t* left, const int32_t* right, int32_t n_sliced,
                       const int64_t* sliced) {
     memset(g, 0, sizeof *g);
-    if (n_leaves < 1 || !rank || !idx_dim || (n_leaves > 1 && (!left || !right)))
+    if (n_leaves < 1 || !rank || (n_idx > 0 && !idx_dim) || (n_leaves > 1 && (!left || !right)))
         return fail("null or empty network");
     g->n_leaves = n_leaves; g->n_idx = n_idx; g->n_out = n_out; g->n_sliced = n_sliced;
     g->rank = rank; g->leaf_idx = leaf_idx; g->idx_dim = idx_dim; g->out_idx = out_idx;

@@ -1,0 +1,479 @@
+// C-ABI entry points of libtn: plan creation, sliced/unsliced contraction,
+// reverse mode, autotuning, and the launch machinery behind them.
+//
+// A call uploads the leaf/output pointer table and the slice-id list into the
+// caller's workspace, then runs the plan's program once per batch of
+// in-flight slices.  The per-batch program (every node contraction for all
+// in-flight slices, the fixed-order FP64 accumulation of their roots and the
+// advance of the device-side batch counter) is captured once into a HIP graph
+// per (mode, workspace) and replayed for every batch, so the host issues one
+// graph launch per batch and never waits on the GPU.  Kernels read the slice
+// id of their in-flight slice from the workspace (slice list indexed by the
+// batch counter), so the same graph serves every batch and every call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+using namespace tn;
+
+static thread_local std::string g_err;
+
+static int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return set_err(TN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
+
+extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* leaf_idx, int32_t n_idx,
+                       const int64_t* idx_dim, int32_t n_out, const int64_t* out_idx, const int32_t* left,
+                       const int32_t* right, int32_t n_sliced, const int64_t* sliced_idx,
+                       const tn_options* opt, tn_plan_t* plan) {
+  g_err.clear();
+  if (!plan) return set_err(TN_E_INVALID, "plan is null");
+  *plan = nullptr;
+  if (n_leaves < 1 || !rank || (n_idx > 0 && !idx_dim) || n_idx < 0 || n_out < 0 || n_sliced < 0)
+    return set_err(TN_E_INVALID, "null or empty network");
+  if (n_leaves > 1 && (!left || !right)) return set_err(TN_E_INVALID, "tree is null");
+  if ((n_out > 0 && !out_idx) || (n_sliced > 0 && !sliced_idx)) return set_err(TN_E_INVALID, "null index list");
+  int64_t tot = 0;
+  for (int v = 0; v < n_leaves; v++) {
+    if (rank[v] < 0 || rank[v] > 64) return set_err(TN_E_INVALID, "leaf rank out of range");
+    tot += rank[v];
+  }
+  if (tot > 0 && !leaf_idx) return set_err(TN_E_INVALID, "leaf index list is null");
+  tn_plan_s* p = new tn_plan_s();
+  p->n_leaves = n_leaves;
+  p->n_idx = n_idx;
+  p->n_out = n_out;
+  p->n_sliced = n_sliced;
+  p->rank.assign(rank, rank + n_leaves);
+  p->leaf_idx.assign(leaf_idx, leaf_idx + tot);
+  p->idx_dim.assign(idx_dim, idx_dim + n_idx);
+  if (n_out) p->out_idx.assign(out_idx, out_idx + n_out);
+  if (n_sliced) p->sliced.assign(sliced_idx, sliced_idx + n_sliced);
+  if (n_leaves > 1) {
+    p->left.assign(left, left + n_leaves - 1);
+    p->right.assign(right, right + n_leaves - 1);
+  }
+  if (opt) p->opt = *opt;
+  p->prec = p->opt.prec;
+  if (p->prec < TN_C64_4M || p->prec > TN_C128) {
+    delete p;
+    return set_err(TN_E_INVALID, "unknown precision");
+  }
+  p->elem_bytes = p->prec == TN_C128 ? 16 : 8;
+  std::string err;
+  int rc = build_plan(p, err);
+  if (rc) {
+    delete p;
+    return set_err(rc, err);
+  }
+  *plan = p;
+  return TN_OK;
+}
+
+extern "C" int tn_plan_info(tn_plan_t p, int32_t* W, int32_t* W_s, double* log2_C, double* flops_8C_per_slice,
+                            int64_t* d_sliced, uint64_t* workspace_bytes) {
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (W) *W = p->W;
+  if (W_s) *W_s = p->W_s;
+  if (log2_C) *log2_C = p->log2_C;
+  if (flops_8C_per_slice) *flops_8C_per_slice = p->flops_per_slice;
+  if (d_sliced) *d_sliced = p->d_sliced;
+  if (workspace_bytes) *workspace_bytes = p->workspace_bytes;
+  return TN_OK;
+}
+
+static int ensure_backward(tn_plan_s* p, int32_t n_wrt, const int32_t* wrt) {
+  if (n_wrt < 0 || (n_wrt > 0 && !wrt)) return set_err(TN_E_INVALID, "null wrt list");
+  std::vector<int32_t> w(wrt, wrt + n_wrt);
+  if (p->bwd_built && w == p->bwd_wrt) return TN_OK;
+  std::string err;
+  int rc = build_backward(p, w, err);
+  if (rc) return set_err(rc, err);
+  // the cached backward graphs belong to the previous wrt set
+  for (auto it = p->graphs.begin(); it != p->graphs.end();) {
+    if (it->first.first == 2) {
+      (void)hipGraphExecDestroy((hipGraphExec_t)it->second);
+      it = p->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return TN_OK;
+}
+
+extern "C" int tn_plan_backward_info(tn_plan_t p, int32_t n_wrt, const int32_t* wrt, uint64_t* workspace_bytes,
+                                     double* flops_per_slice) {
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  int rc = ensure_backward(p, n_wrt, wrt);
+  if (rc) return rc;
+  if (workspace_bytes) *workspace_bytes = p->bwd_workspace_bytes;
+  if (flops_per_slice) *flops_per_slice = p->bwd_flops_per_slice;
+  return TN_OK;
+}
+
+extern "C" int tn_plan_num_nodes(tn_plan_t p, int32_t* n) {
+  if (!p || !n) return set_err(TN_E_INVALID, "null pointer");
+  *n = (int32_t)p->nodes.size();
+  return TN_OK;
+}
+
+extern "C" int tn_plan_node_info(tn_plan_t p, int32_t k, int32_t* kernel_class, int32_t* logH, int32_t* logM,
+                                 int32_t* logN, int32_t* logK, double* flops, double* bytes) {
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (k < 0 || k >= (int32_t)p->nodes.size()) return set_err(TN_E_INVALID, "node out of range");
+  const NodeInfo& ni = p->nodes[k];
+  if (kernel_class) *kernel_class = ni.kclass;
+  if (logH) *logH = (int32_t)ni.H.size();
+  if (logM) *logM = (int32_t)ni.M.size();
+  if (logN) *logN = (int32_t)ni.N.size();
+  if (logK) *logK = (int32_t)ni.K.size();
+  if (flops) *flops = ni.flops;
+  if (bytes) *bytes = ni.bytes;
+  return TN_OK;
+}
+
+// ------------------------------------------------------------------ launching
+
+static Ctx make_ctx(const tn_plan_s* p, void* ws, uint64_t arena_stride) {
+  Ctx c;
+  std::memset(&c, 0, sizeof c);
+  c.ws = reinterpret_cast<uint64_t>(ws);
+  c.arena_stride = arena_stride;
+  c.ptrtab_off = p->ptrtab_off;
+  c.sid_off = p->sid_off;
+  c.counter_off = p->counter_off;
+  c.arena_off = p->arena_off;
+  c.n_batch = p->n_batch;
+  c.elem_bytes = p->elem_bytes;
+  return c;
+}
+
+static hipError_t launch_op(const tn_plan_s* p, const Ctx& ctx, const Op& op, hipStream_t s) {
+  const bool f64 = p->prec == TN_C128;
+  switch (op.kind) {
+    case OpKind::Row: return launch_row(ctx, op.row, f64, s);
+    case OpKind::RowReduce: return launch_reduce(ctx, op.row, f64, s);
+    case OpKind::Gemm: return launch_gemm(ctx, op.gemm, p->prec, s);
+    case OpKind::Accum: return launch_accum(ctx, op.accum, f64, s);
+    case OpKind::Permute: return launch_permute(ctx, op.perm, f64, s);
+    case OpKind::Fill: return hipSuccess;
+    case OpKind::Counter: return launch_counter(ctx, 1, 1, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Tail of the forward program: what happens to each in-flight slice's root.
+// mode 0: copy to the output slot in the storage type (unsliced contraction)
+// mode 1: FP64 accumulation into the complex128 output slot
+static std::vector<Op> forward_program(const tn_plan_s* p, int mode) {
+  std::vector<Op> prog = p->fwd;
+  const int n = p->n_leaves;
+  Ref root;
+  std::memset(&root, 0, sizeof root);
+  std::vector<int8_t> src_pos;
+  int nb = 0;
+  if (n > 1) {
+    root.kind = 1;
+    root.off = p->root_off;
+    nb = (int)p->kept_bits[2 * n - 2].size();
+    for (int i = 0; i < nb; i++) src_pos.push_back((int8_t)i);
+  } else {
+    // a single leaf: its axes are all outputs; read it in output order
+    root.kind = 0;
+    root.slot = 0;
+    const Layout& L = p->layout[0];
+    std::vector<int> outbits;
+    for (int i = p->n_out - 1; i >= 0; i--) {
+      int64_t e = p->out_idx[i];
+      for (int s = 0; s < p->bit_count[e]; s++) outbits.push_back(p->bit_base[e] + s);
+    }
+    nb = (int)outbits.size();
+    for (int b : outbits) src_pos.push_back((int8_t)L.pos_of(b));
+  }
+  Op t;
+  std::memset(&t.perm, 0, sizeof t.perm);
+  std::memset(&t.accum, 0, sizeof t.accum);
+  if (mode == 0 || n == 1) {
+    t.kind = OpKind::Permute;
+    t.perm.src = root;
+    t.perm.dst.kind = 2;
+    t.perm.dst.slot = p->slot_out;
+    t.perm.n_bits = nb;
+    t.perm.src_c128 = p->prec == TN_C128;
+    t.perm.dst_c128 = mode == 1 ? 1 : (p->prec == TN_C128);
+    t.perm.accumulate = mode == 1 ? 1 : 0;
+    t.perm.per_slice_serial = mode == 1 ? 1 : 0;
+    for (int i = 0; i < nb; i++) { t.perm.src_pos[i] = src_pos[i]; t.perm.dst_pos[i] = (int8_t)i; }
+  } else {
+    t.kind = OpKind::Accum;
+    t.accum.src = root;
+    t.accum.dst.kind = 2;
+    t.accum.dst.slot = p->slot_out;
+    t.accum.n = int64_t(1) << nb;
+  }
+  prog.push_back(t);
+  Op c;
+  c.kind = OpKind::Counter;
+  prog.push_back(c);
+  return prog;
+}
+
+static std::vector<Op> backward_program(const tn_plan_s* p) {
+  std::vector<Op> prog = p->bwd;
+  Op c;
+  c.kind = OpKind::Counter;
+  prog.push_back(c);
+  return prog;
+}
+
+static bool graphs_enabled() {
+  const char* e = std::getenv("TN_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+static hipStream_t capture_stream() {
+  static thread_local hipStream_t s = nullptr;
+  if (!s) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  }
+  return s;
+}
+
+// Run `prog` n_batches times on stream s (graph replay when enabled).
+static int run_batches(tn_plan_s* p, int mode, const std::vector<Op>& prog, const Ctx& ctx, int64_t n_batches,
+                       hipStream_t s) {
+  if (n_batches <= 0) return TN_OK;
+  if (graphs_enabled()) {
+    auto key = std::make_pair(mode, ctx.ws);
+    auto it = p->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == p->graphs.end()) {
+      hipStream_t cs = capture_stream();
+      if (!cs) return set_err(TN_E_DEVICE, "could not create the capture stream");
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      for (const Op& op : prog) {
+        hipError_t e = launch_op(p, ctx, op, cs);
+        if (e != hipSuccess) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cs, &g);
+          if (g) (void)hipGraphDestroy(g);
+          return set_err(TN_E_DEVICE, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+        }
+      }
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamEndCapture(cs, &graph));
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return set_err(TN_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      p->graphs[key] = exec;
+    } else {
+      exec = (hipGraphExec_t)it->second;
+    }
+    for (int64_t b = 0; b < n_batches; b++) HIP_TRY(hipGraphLaunch(exec, s));
+    return TN_OK;
+  }
+  for (int64_t b = 0; b < n_batches; b++)
+    for (const Op& op : prog) {
+      hipError_t e = launch_op(p, ctx, op, s);
+      if (e != hipSuccess) return set_err(TN_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+  return TN_OK;
+}
+
+// Upload the pointer table and the (padded) slice ids; reset the batch counter.
+static int upload(tn_plan_s* p, void* ws, const void* const* leaves, void* out, const void* gout,
+                  void* const* grads, int n_grads, const std::vector<int64_t>& ids, hipStream_t s) {
+  std::vector<uint64_t> tab(p->n_slots, 0);
+  for (int v = 0; v < p->n_leaves; v++) tab[v] = reinterpret_cast<uint64_t>(leaves[v]);
+  tab[p->slot_out] = reinterpret_cast<uint64_t>(out);
+  tab[p->slot_gout] = reinterpret_cast<uint64_t>(gout);
+  for (int i = 0; i < n_grads; i++) tab[p->slot_grad0 + i] = reinterpret_cast<uint64_t>(grads[i]);
+  char* w = static_cast<char*>(ws);
+  HIP_TRY(hipMemcpyAsync(w + p->ptrtab_off, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(w + p->sid_off, ids.data(), ids.size() * 8, hipMemcpyHostToDevice, s));
+  Ctx ctx = make_ctx(p, ws, 0);
+  HIP_TRY(launch_counter(ctx, 0, 0, s));
+  return TN_OK;
+}
+
+static int check_leaves(const tn_plan_s* p, const void* const* leaves) {
+  if (!leaves) return set_err(TN_E_INVALID, "leaves is null");
+  for (int v = 0; v < p->n_leaves; v++)
+    if (!leaves[v]) return set_err(TN_E_INVALID, "leaf " + std::to_string(v) + " is null");
+  return TN_OK;
+}
+
+static int make_ids(const tn_plan_s* p, int64_t n_ids, const int64_t* slice_ids, std::vector<int64_t>& ids) {
+  if (slice_ids == nullptr) {
+    if (p->d_sliced > p->max_ids)
+      return set_err(TN_E_INVALID, "too many slices for one call; pass slice_ids in chunks");
+    ids.resize(p->d_sliced);
+    for (int64_t i = 0; i < p->d_sliced; i++) ids[i] = i;
+  } else {
+    if (n_ids < 0) return set_err(TN_E_INVALID, "negative n_ids");
+    if (n_ids > p->max_ids) return set_err(TN_E_INVALID, "too many slice ids for one call (max " + std::to_string(p->max_ids) + ")");
+    ids.assign(slice_ids, slice_ids + n_ids);
+    for (int64_t x : ids)
+      if (x < 0 || x >= p->d_sliced) return set_err(TN_E_INVALID, "slice id " + std::to_string(x) + " out of range");
+  }
+  const int64_t nb = p->n_batch;
+  const int64_t padded = (int64_t)((ids.size() + nb - 1) / nb * nb);
+  ids.resize(padded, -1);
+  return TN_OK;
+}
+
+extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_t n_ids, const int64_t* slice_ids,
+                                  void* out_c128, void* workspace, uint64_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (!out_c128) return set_err(TN_E_INVALID, "output is null");
+  int rc = check_leaves(p, leaves);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < p->workspace_bytes)
+    return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->workspace_bytes) + " bytes required");
+  std::vector<int64_t> ids;
+  rc = make_ids(p, n_ids, slice_ids, ids);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = upload(p, workspace, leaves, out_c128, nullptr, nullptr, 0, ids, s);
+  if (rc) return rc;
+  const int64_t out_elems = int64_t(1) << (p->n_leaves > 1 ? p->kept_bits[2 * p->n_leaves - 2].size()
+                                                           : p->layout[0].bits.size());
+  HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(out_c128), (uint64_t)out_elems * 16, s));
+  Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
+  return run_batches(p, 1, forward_program(p, 1), ctx, (int64_t)ids.size() / p->n_batch, s);
+}
+
+extern "C" int tn_contract(tn_plan_t p, const void* const* leaves, void* out, void* workspace,
+                           uint64_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (p->n_sliced > 0) return set_err(TN_E_INVALID, "plan has sliced indices; use tn_contract_sliced");
+  if (!out) return set_err(TN_E_INVALID, "output is null");
+  int rc = check_leaves(p, leaves);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < p->workspace_bytes)
+    return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->workspace_bytes) + " bytes required");
+  std::vector<int64_t> ids;
+  rc = make_ids(p, 1, std::vector<int64_t>{0}.data(), ids);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = upload(p, workspace, leaves, out, nullptr, nullptr, 0, ids, s);
+  if (rc) return rc;
+  Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
+  return run_batches(p, 0, forward_program(p, 0), ctx, (int64_t)ids.size() / p->n_batch, s);
+}
+
+extern "C" int tn_contract_backward(tn_plan_t p, const void* const* leaves, const void* grad_out_c128,
+                                    int32_t n_wrt, const int32_t* wrt_leaf, void* const* grads, int64_t n_ids,
+                                    const int64_t* slice_ids, void* workspace, uint64_t workspace_bytes,
+                                    void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (!grad_out_c128) return set_err(TN_E_INVALID, "grad_out is null");
+  if (n_wrt > 0 && !grads) return set_err(TN_E_INVALID, "grads is null");
+  int rc = check_leaves(p, leaves);
+  if (rc) return rc;
+  for (int i = 0; i < n_wrt; i++)
+    if (!grads[i]) return set_err(TN_E_INVALID, "grads[" + std::to_string(i) + "] is null");
+  rc = ensure_backward(p, n_wrt, wrt_leaf);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < p->bwd_workspace_bytes)
+    return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->bwd_workspace_bytes) + " bytes required");
+  std::vector<int64_t> ids;
+  rc = make_ids(p, n_ids, slice_ids, ids);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = upload(p, workspace, leaves, nullptr, grad_out_c128, grads, n_wrt, ids, s);
+  if (rc) return rc;
+  for (int i = 0; i < n_wrt; i++) {
+    int v = wrt_leaf[i];
+    int64_t elems = 1;
+    for (int a = 0; a < p->rank[v]; a++) elems *= p->idx_dim[p->leaf_idx[p->leaf_off[v] + a]];
+    HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(grads[i]), (uint64_t)elems * p->elem_bytes, s));
+  }
+  if (n_wrt == 0) return TN_OK;
+  Ctx ctx = make_ctx(p, workspace, p->bwd_arena_bytes);
+  return run_batches(p, 2, backward_program(p), ctx, (int64_t)ids.size() / p->n_batch, s);
+}
+
+// ------------------------------------------------------------------ autotuning
+
+// For every distinct matrix-core contraction shape, time each tile variant on
+// the plan's own operands (zero-filled arena) and keep the fastest.
+extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (!workspace || workspace_bytes < p->workspace_bytes)
+    return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->workspace_bytes) + " bytes required");
+  if (p->prec == TN_C128) return TN_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int64_t> ids(p->n_batch, 0);
+  ids.resize((size_t)std::max<int64_t>(p->n_batch, 1), 0);
+  for (size_t i = 1; i < ids.size(); i++) ids[i] = -1;   // one live slice
+  std::vector<const void*> dummy(p->n_leaves, workspace);
+  int rc = upload(p, workspace, dummy.data(), workspace, nullptr, nullptr, 0, ids, s);
+  if (rc) return rc;
+  HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(workspace) + p->arena_off, p->arena_bytes, s));
+  Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct Key { int h, m, n, k; bool operator<(const Key& o) const { return std::tie(h, m, n, k) < std::tie(o.h, o.m, o.n, o.k); } };
+  std::map<Key, int> best;
+  for (Op& op : p->fwd) {
+    if (op.kind != OpKind::Gemm) continue;
+    GemmOp& g = op.gemm;
+    if (g.a.kind != 1 || g.b.kind != 1) continue;   // leaf operands: keep the default
+    Key key{g.n_h, g.n_m, g.n_n, g.n_k};
+    auto it = best.find(key);
+    if (it != best.end()) { g.tile = it->second; continue; }
+    float best_ms = 1e30f;
+    int best_tile = 0;
+    for (int t = 0; t < kNumGemmTiles; t++) {
+      GemmOp trial = g;
+      trial.tile = t;
+      const int reps = 3;
+      HIP_TRY(launch_gemm(ctx, trial, p->prec, s));   // warm-up
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; r++) HIP_TRY(launch_gemm(ctx, trial, p->prec, s));
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) { best_ms = ms; best_tile = t; }
+    }
+    g.tile = best_tile;
+    best[key] = best_tile;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  p->graphs.clear();
+  p->tuned = true;
+  return TN_OK;
+}
+
+extern "C" void tn_plan_destroy(tn_plan_t p) {
+  if (!p) return;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  delete p;
+}

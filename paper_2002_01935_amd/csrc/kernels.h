@@ -1,0 +1,22 @@
+// Launchers for the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/tn.h"
+#include "tn_internal.h"
+
+namespace tn {
+
+hipError_t launch_row(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s);
+hipError_t launch_reduce(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s);
+hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s);
+hipError_t launch_permute(const Ctx& ctx, const PermuteOp& op, bool f64, hipStream_t s);
+hipError_t launch_accum(const Ctx& ctx, const AccumOp& op, bool f64, hipStream_t s);
+hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s);
+hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s);
+// log2 tile sizes of a gemm tile variant; -1 if unknown
+int gemm_tile_bits(int tile, int* bm, int* bn);
+constexpr int kNumGemmTiles = 5;
+
+}  // namespace tn

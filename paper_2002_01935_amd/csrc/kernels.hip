@@ -1,0 +1,740 @@
+// gfx950 kernels for pairwise tensor contraction (Sec. 2: a vertex
+// contraction is the product of two tensors summed over their common,
+// no-longer-needed indices).
+//
+// Every operand is addressed through bit positions (tn_internal.h): element
+// offset = sum over bit indices of (bit << position).  Loads therefore read an
+// operand in whatever axis order it is stored and writes produce the order
+// the consumer asked for; no transpose is ever materialised.
+//
+// Kernel classes:
+//   row_kernel     one thread per output "row" (batch + large free side), the
+//                  small free side (<= 16 values) and the summed range inside
+//                  the thread; bandwidth-bound gate applications and
+//                  absorptions of small tensors into large ones.
+//   splitk_kernel  one 64-lane wavefront per (row, K chunk), lanes striding
+//                  over the summed indices; long reductions with few outputs
+//                  (dot products, skinny contractions).  Chunks are reduced in
+//                  a fixed order by reduce_kernel, so results are
+//                  deterministic.
+//   gemm_mfma_4m   complex GEMM on FP32 matrix cores: the complex product is
+//                  embedded as a real product of [Ar Ai] (M x 2K) with
+//                  [[Br Bi] [-Bi Br]] (2K x 2N), so one v_mfma_f32_32x32x2f32
+//                  with k = (re, im) is one complex multiply-add of a 32 x 16
+//                  complex tile: 4 real products (4M), FP32 accumulation.
+//   gemm_valu      tiled vector-ALU complex GEMM, used for complex128.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace tn {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T> struct C2;
+template <> struct C2<float> { using t = float2; };
+template <> struct C2<double> { using t = double2; };
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+template <typename V>
+__device__ __forceinline__ V cfma(V acc, V a, V b) {
+  acc.x = acc.x + a.x * b.x - a.y * b.y;
+  acc.y = acc.y + a.x * b.y + a.y * b.x;
+  return acc;
+}
+
+__device__ __forceinline__ uint64_t deposit(uint64_t v, const int8_t* pos, int n) {
+  uint64_t off = 0;
+  for (int i = 0; i < n; i++)
+    if ((v >> i) & 1) off |= uint64_t(1) << pos[i];
+  return off;
+}
+
+// position list may hold -1 (bit absent from this operand)
+__device__ __forceinline__ uint64_t deposit_opt(uint64_t v, const int8_t* pos, int n) {
+  uint64_t off = 0;
+  for (int i = 0; i < n; i++)
+    if (((v >> i) & 1) && pos[i] >= 0) off |= uint64_t(1) << pos[i];
+  return off;
+}
+
+__device__ __forceinline__ int64_t slice_id(const Ctx& ctx, int z) {
+  const int64_t cnt = *reinterpret_cast<const int64_t*>(ctx.ws + ctx.counter_off);
+  const int64_t* sids = reinterpret_cast<const int64_t*>(ctx.ws + ctx.sid_off);
+  return sids[cnt * ctx.n_batch + z];
+}
+
+// Base address of an operand for in-flight slice z with slice id sid.
+__device__ __forceinline__ char* resolve(const Ctx& ctx, const Ref& r, int z, int64_t sid, int ebytes) {
+  if (r.kind == 1)
+    return reinterpret_cast<char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
+  const uint64_t p = reinterpret_cast<const uint64_t*>(ctx.ws + ctx.ptrtab_off)[r.slot];
+  uint64_t off = 0;
+  for (int i = 0; i < r.n_slice; i++)
+    if ((sid >> r.slice_bit[i]) & 1) off |= uint64_t(1) << r.slice_pos[i];
+  return reinterpret_cast<char*>(p) + off * uint64_t(ebytes);
+}
+
+template <typename V>
+__device__ __forceinline__ V conjv(V a, int c) {
+  if (c) a.y = -a.y;
+  return a;
+}
+
+// ------------------------------------------------------------------ row kernel
+
+constexpr int kRowThreads = 256;
+constexpr int kKTabBits = 10;
+
+template <typename T, int NIN>
+__global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  __shared__ uint32_t ktab_a[1 << kKTabBits];
+  __shared__ uint32_t ktab_b[1 << kKTabBits];
+  const int klo = op.n_k < kKTabBits ? op.n_k : kKTabBits;
+  for (int k = threadIdx.x; k < (1 << klo); k += blockDim.x) {
+    ktab_a[k] = (uint32_t)deposit(k, op.k_a, klo);
+    ktab_b[k] = (uint32_t)deposit(k, op.k_b, klo);
+  }
+  __syncthreads();
+  const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >> op.n_rows) return;
+  const int eb = sizeof(V);
+  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb));
+  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb));
+  V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+  const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
+  const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
+  const uint64_t oc = deposit(row, op.row_c, op.n_rows);
+  uint64_t inb[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) inb[j] = deposit(j, op.in_b, op.n_in);
+  V acc[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { acc[j].x = 0; acc[j].y = 0; }
+  const uint64_t nk = uint64_t(1) << op.n_k;
+  const uint64_t lomask = (uint64_t(1) << klo) - 1;
+  uint64_t hia = 0, hib = 0;
+  for (uint64_t k = 0; k < nk; k++) {
+    if ((k & lomask) == 0 && k) {
+      hia = deposit(k >> klo, op.k_a + klo, op.n_k - klo);
+      hib = deposit(k >> klo, op.k_b + klo, op.n_k - klo);
+    }
+    const V a = conjv(A[oa + hia + ktab_a[k & lomask]], op.conj_a);
+    const uint64_t bb = ob + hib + ktab_b[k & lomask];
+#pragma unroll
+    for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a, conjv(B[bb + inb[j]], op.conj_b));
+  }
+#pragma unroll
+  for (int j = 0; j < NIN; j++) {
+    const uint64_t c = oc + deposit(j, op.in_c, op.n_in);
+    if (op.accumulate) {
+      V o = Cp[c];
+      o.x += acc[j].x;
+      o.y += acc[j].y;
+      Cp[c] = o;
+    } else {
+      Cp[c] = acc[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ split-K
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  // fixed butterfly order: identical result on every run
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, int NIN>
+__global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  __shared__ uint32_t ktab_a[1 << kKTabBits];
+  __shared__ uint32_t ktab_b[1 << kKTabBits];
+  const int klo = op.n_k < kKTabBits ? op.n_k : kKTabBits;
+  for (int k = threadIdx.x; k < (1 << klo); k += blockDim.x) {
+    ktab_a[k] = (uint32_t)deposit(k, op.k_a, klo);
+    ktab_b[k] = (uint32_t)deposit(k, op.k_b, klo);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+  const uint64_t row = wave >> ks;
+  const uint64_t chunk = wave & ((uint64_t(1) << ks) - 1);
+  if (row >> op.n_rows) return;
+  const int eb = sizeof(V);
+  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb));
+  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb));
+  const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
+  const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
+  uint64_t inb[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) inb[j] = deposit(j, op.in_b, op.n_in);
+  T ar[NIN], ai[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { ar[j] = 0; ai[j] = 0; }
+  const int cbits = op.n_k - ks;                  // >= 6
+  const uint64_t csize = uint64_t(1) << cbits;
+  const uint64_t k0 = chunk << cbits;
+  const uint64_t lomask = (uint64_t(1) << klo) - 1;
+  uint64_t cur_hi = ~uint64_t(0), hia = 0, hib = 0;
+  for (uint64_t kk = lane; kk < csize; kk += 64) {
+    const uint64_t k = k0 + kk;
+    const uint64_t hi = k >> klo;
+    if (hi != cur_hi) {
+      cur_hi = hi;
+      hia = deposit(hi, op.k_a + klo, op.n_k - klo);
+      hib = deposit(hi, op.k_b + klo, op.n_k - klo);
+    }
+    const V a = conjv(A[oa + hia + ktab_a[k & lomask]], op.conj_a);
+    const uint64_t bb = ob + hib + ktab_b[k & lomask];
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      const V b = conjv(B[bb + inb[j]], op.conj_b);
+      ar[j] += a.x * b.x - a.y * b.y;
+      ai[j] += a.x * b.y + a.y * b.x;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { ar[j] = wave_sum(ar[j]); ai[j] = wave_sum(ai[j]); }
+  if (lane != 0) return;
+  if (ks == 0) {
+    V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+    const uint64_t oc = deposit(row, op.row_c, op.n_rows);
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      const uint64_t c = oc + deposit(j, op.in_c, op.n_in);
+      V o;
+      o.x = ar[j];
+      o.y = ai[j];
+      if (op.accumulate) { V p = Cp[c]; o.x += p.x; o.y += p.y; }
+      Cp[c] = o;
+    }
+  } else {
+    V* P = reinterpret_cast<V*>(resolve(ctx, op.part, z, sid, eb));
+    const uint64_t base = ((chunk << op.n_rows) + row) * NIN;
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      V o;
+      o.x = ar[j];
+      o.y = ai[j];
+      P[base + j] = o;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int nin = 1 << op.n_in;
+  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t row = t / nin;
+  const int j = (int)(t % nin);
+  if (row >> op.n_rows) return;
+  const int eb = sizeof(V);
+  const V* P = reinterpret_cast<const V*>(resolve(ctx, op.part, z, sid, eb));
+  V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+  V s;
+  s.x = 0;
+  s.y = 0;
+  const uint64_t nch = uint64_t(1) << op.k_split_bits;
+  for (uint64_t ch = 0; ch < nch; ch++) {
+    const V p = P[((ch << op.n_rows) + row) * nin + j];
+    s.x += p.x;
+    s.y += p.y;
+  }
+  const uint64_t c = deposit(row, op.row_c, op.n_rows) + deposit(j, op.in_c, op.n_in);
+  if (op.accumulate) { V p = Cp[c]; s.x += p.x; s.y += p.y; }
+  Cp[c] = s;
+}
+
+// ------------------------------------------------------------------ permute / accumulate
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void permute_kernel(Ctx ctx, PermuteOp op) {
+  using VS = typename C2<TS>::t;
+  using VD = typename C2<TD>::t;
+  const uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >> op.n_bits) return;
+  const uint64_t so = deposit(e, op.src_pos, op.n_bits);
+  const uint64_t dof = deposit(e, op.dst_pos, op.n_bits);
+  const int z0 = op.per_slice_serial ? 0 : blockIdx.y;
+  const int z1 = op.per_slice_serial ? ctx.n_batch : blockIdx.y + 1;
+  for (int z = z0; z < z1; z++) {
+    const int64_t sid = slice_id(ctx, z);
+    if (sid < 0) continue;
+    const VS* S = reinterpret_cast<const VS*>(resolve(ctx, op.src, z, sid, sizeof(VS)));
+    VD* D = reinterpret_cast<VD*>(resolve(ctx, op.dst, z, sid, sizeof(VD)));
+    const VS s = S[so];
+    VD d;
+    if (op.accumulate) {
+      d = D[dof];
+      d.x += (TD)s.x;
+      d.y += (TD)s.y;
+    } else {
+      d.x = (TD)s.x;
+      d.y = (TD)s.y;
+    }
+    D[dof] = d;
+  }
+}
+
+// dst (complex128) += root of every in-flight slice, one slice after the
+// other in slice order: the FP64 sum has the same rounding whatever the batch.
+template <typename T>
+__global__ __launch_bounds__(256) void accum_kernel(Ctx ctx, AccumOp op) {
+  using V = typename C2<T>::t;
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= op.n) return;
+  double2* D = reinterpret_cast<double2*>(resolve(ctx, op.dst, 0, 0, 16));
+  double2 d = D[o];
+  for (int z = 0; z < ctx.n_batch; z++) {
+    const int64_t sid = slice_id(ctx, z);
+    if (sid < 0) continue;
+    const V* S = reinterpret_cast<const V*>(resolve(ctx, op.src, z, sid, sizeof(V)));
+    const V s = S[o];
+    d.x += (double)s.x;
+    d.y += (double)s.y;
+  }
+  D[o] = d;
+}
+
+__global__ void counter_kernel(Ctx ctx, int64_t value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t* c = reinterpret_cast<int64_t*>(ctx.ws + ctx.counter_off);
+    *c = add ? *c + value : value;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(uint64_t base, uint64_t n_words) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_words) reinterpret_cast<uint64_t*>(base)[i] = 0;
+}
+
+// ------------------------------------------------------------------ tile loaders
+
+// Enumerates the elements of an R x Kt tile of a bit-addressed operand in the
+// order of their memory addresses (tile bits sorted by position), so that
+// consecutive threads touch consecutive addresses whenever the operand's
+// lowest bits lie inside the tile; returns the element offset within the tile
+// and its (row, k) position in the tile.
+struct TileMap {
+  int nbits;
+  int8_t pos[kMaxTileBits];   // position in the operand of enumeration bit i
+  int8_t dst[kMaxTileBits];   // destination bit in the tile index (k * R + row)
+};
+
+__device__ __forceinline__ void make_tilemap(TileMap& tm, const int8_t* rowpos, int rbits,
+                                             const int8_t* kpos, int kbits, int rlog) {
+  // gather (position, destination) pairs and sort by position (tiny insertion sort)
+  int n = 0;
+  for (int i = 0; i < rbits; i++) { tm.pos[n] = rowpos[i]; tm.dst[n] = (int8_t)i; n++; }
+  for (int i = 0; i < kbits; i++) { tm.pos[n] = kpos[i]; tm.dst[n] = (int8_t)(rlog + i); n++; }
+  for (int i = 1; i < n; i++) {
+    int8_t p = tm.pos[i], d = tm.dst[i];
+    int j = i - 1;
+    while (j >= 0 && tm.pos[j] > p) { tm.pos[j + 1] = tm.pos[j]; tm.dst[j + 1] = tm.dst[j]; j--; }
+    tm.pos[j + 1] = p;
+    tm.dst[j + 1] = d;
+  }
+  tm.nbits = n;
+}
+
+// ------------------------------------------------------------------ MFMA 4M
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// BM x BN complex output tile per 256-thread block (2 x 2 waves), BK complex
+// k values per pipeline stage.
+template <int BM, int BN, int BK>
+__global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 32, FN = WN / 16;        // 32x32x2 fragments per wave
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = __builtin_ctz(BK);
+  static_assert(FM >= 1 && FN >= 1 && LA >= 1 && LB >= 1, "tile too small");
+  __shared__ float lds[2][2][BK][BM + BN];          // [buffer][re/im][k][A rows | B cols]
+
+  const int nzh = ctx.n_batch;
+  const int z = blockIdx.y % nzh;
+  const uint64_t h = blockIdx.y / nzh;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+
+  const int tm = op.n_m < RM ? op.n_m : RM;
+  const int tn = op.n_n < RN ? op.n_n : RN;
+  const int tk = op.n_k < RK ? op.n_k : RK;
+  // XCD-aware tile order: consecutive block ids go to different XCDs (8), so
+  // give each XCD a contiguous range of tiles (shared A rows / B columns in
+  // its L2)
+  const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
+  const uint64_t ntiles = (uint64_t(1) << (op.n_m - tm)) * ntiles_n;
+  uint64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const uint64_t tile_m = bid / ntiles_n, tile_n = bid % ntiles_n;
+
+  const char* Ab = resolve(ctx, op.a, z, sid, 8);
+  const char* Bb = resolve(ctx, op.b, z, sid, 8);
+  char* Cb = resolve(ctx, op.c, z, sid, 8);
+  const float2* A = reinterpret_cast<const float2*>(Ab) + deposit(h, op.a_h, op.n_h) +
+                    deposit(tile_m, op.a_m + tm, op.n_m - tm);
+  const float2* B = reinterpret_cast<const float2*>(Bb) + deposit(h, op.b_h, op.n_h) +
+                    deposit(tile_n, op.b_n + tn, op.n_n - tn);
+
+  // per-thread load slots: offset in the operand and place in the tile
+  TileMap ma, mb;
+  make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
+  make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
+  const int tid = threadIdx.x;
+  uint32_t a_off[LA], b_off[LB];
+  int16_t a_dst[LA], b_dst[LB];
+#pragma unroll
+  for (int i = 0; i < LA; i++) {
+    const int e = tid + 256 * i;
+    uint32_t off = 0;
+    int d = 0;
+    bool ok = (e >> ma.nbits) == 0;
+    for (int b = 0; b < ma.nbits; b++)
+      if ((e >> b) & 1) { off |= 1u << ma.pos[b]; d |= 1 << ma.dst[b]; }
+    a_off[i] = off;
+    a_dst[i] = ok ? (int16_t)d : (int16_t)-1;
+  }
+#pragma unroll
+  for (int i = 0; i < LB; i++) {
+    const int e = tid + 256 * i;
+    uint32_t off = 0;
+    int d = 0;
+    bool ok = (e >> mb.nbits) == 0;
+    for (int b = 0; b < mb.nbits; b++)
+      if ((e >> b) & 1) { off |= 1u << mb.pos[b]; d |= 1 << mb.dst[b]; }
+    b_off[i] = off;
+    b_dst[i] = ok ? (int16_t)d : (int16_t)-1;
+  }
+  // zero both buffers once (covers partial tiles)
+  for (int i = tid; i < 2 * 2 * BK * (BM + BN); i += 256) (&lds[0][0][0][0])[i] = 0.f;
+  __syncthreads();
+
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - tk);
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  float2 ra[LA], rb[LB];
+  auto gload = [&](uint64_t step) {
+    const uint64_t ka = deposit(step, op.a_k + tk, op.n_k - tk);
+    const uint64_t kb = deposit(step, op.b_k + tk, op.n_k - tk);
+#pragma unroll
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) ra[i] = A[ka + a_off[i]];
+#pragma unroll
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) rb[i] = B[kb + b_off[i]];
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) {
+        const int row = a_dst[i] & (BM - 1), k = a_dst[i] >> RM;
+        lds[buf][0][k][row] = ra[i].x;
+        lds[buf][1][k][row] = sa * ra[i].y;
+      }
+#pragma unroll
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) {
+        const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
+        lds[buf][0][k][BM + col] = rb[i].x;
+        lds[buf][1][k][BM + col] = sb * rb[i].y;
+      }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int hi = lane >> 5;                 // 0: real part of k, 1: imaginary part
+  const int c32 = lane & 31;
+  const int bpar = c32 & 1;                 // output column parity: re / im
+  const int bplane = bpar ^ hi;             // which part of B feeds this lane
+  const float bsign = (bpar == 0 && hi == 1) ? -1.f : 1.f;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (uint64_t s = 0; s < nsteps; s++) {
+    const int buf = s & 1;
+    if (s + 1 < nsteps) gload(s + 1);
+#pragma unroll
+    for (int k = 0; k < BK; k++) {
+      float af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; i++) af[i] = lds[buf][hi][k][wm * WM + i * 32 + c32];
+#pragma unroll
+      for (int j = 0; j < FN; j++) bf[j] = bsign * lds[buf][bplane][k][BM + wn * WN + j * 16 + (c32 >> 1)];
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (s + 1 < nsteps) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: C[row, col] at deposit(row, c_m) + deposit(col, c_n) (+ batch)
+  float* C = reinterpret_cast<float*>(Cb);
+  const uint64_t cbase = deposit(h, op.c_h, op.n_h) + deposit(tile_m, op.c_m + tm, op.n_m - tm) +
+                         deposit(tile_n, op.c_n + tn, op.n_n - tn);
+  uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
+  uint64_t* coloff = rowoff + BM;
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+  for (int i = tid; i < BM; i += 256) rowoff[i] = deposit(i, op.c_m, tm);
+  for (int i = tid; i < BN; i += 256) coloff[i] = deposit(i, op.c_n, tn);
+  __syncthreads();
+  const int mvalid = 1 << tm, nvalid = 1 << tn;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      const int col = wn * WN + j * 16 + (c32 >> 1);
+      if (col >= nvalid) continue;
+      const uint64_t co = coloff[col];
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+        if (row >= mvalid) continue;
+        float* dst = C + 2 * (cbase + rowoff[row] + co) + bpar;
+        if (op.accumulate) *dst += acc[i][j][r];
+        else *dst = acc[i][j][r];
+      }
+    }
+}
+
+// ------------------------------------------------------------------ VALU tiled GEMM
+
+// 64 x 64 complex tile, 256 threads, each thread 4 x 4 outputs; used for
+// complex128 and as the FP32 reference variant of the tile autotuner.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
+  using V = typename C2<T>::t;
+  constexpr int BM = 64, BN = 64, BK = 8, RM = 6, RN = 6, RK = 3;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  __shared__ V As[BK][BM];
+  __shared__ V Bs[BK][BN];
+  const int nzh = ctx.n_batch;
+  const int z = blockIdx.y % nzh;
+  const uint64_t h = blockIdx.y / nzh;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int tm = op.n_m < RM ? op.n_m : RM;
+  const int tn = op.n_n < RN ? op.n_n : RN;
+  const int tk = op.n_k < RK ? op.n_k : RK;
+  const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
+  const uint64_t tile_m = blockIdx.x / ntiles_n, tile_n = blockIdx.x % ntiles_n;
+  const int eb = sizeof(V);
+  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, op.n_h) +
+               deposit(tile_m, op.a_m + tm, op.n_m - tm);
+  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, op.n_h) +
+               deposit(tile_n, op.b_n + tn, op.n_n - tn);
+  V* C = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, op.n_h) +
+         deposit(tile_m, op.c_m + tm, op.n_m - tm) + deposit(tile_n, op.c_n + tn, op.n_n - tn);
+  TileMap ma, mb;
+  make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
+  make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
+  const int tid = threadIdx.x;
+  uint64_t a_off[LA], b_off[LB];
+  int a_dst[LA], b_dst[LB];
+  for (int i = 0; i < LA; i++) {
+    const int e = tid + 256 * i;
+    uint64_t off = 0;
+    int d = 0;
+    for (int b = 0; b < ma.nbits; b++)
+      if ((e >> b) & 1) { off |= uint64_t(1) << ma.pos[b]; d |= 1 << ma.dst[b]; }
+    a_off[i] = off;
+    a_dst[i] = (e >> ma.nbits) == 0 ? d : -1;
+  }
+  for (int i = 0; i < LB; i++) {
+    const int e = tid + 256 * i;
+    uint64_t off = 0;
+    int d = 0;
+    for (int b = 0; b < mb.nbits; b++)
+      if ((e >> b) & 1) { off |= uint64_t(1) << mb.pos[b]; d |= 1 << mb.dst[b]; }
+    b_off[i] = off;
+    b_dst[i] = (e >> mb.nbits) == 0 ? d : -1;
+  }
+  for (int i = tid; i < BK * BM; i += 256) { (&As[0][0])[i].x = 0; (&As[0][0])[i].y = 0; }
+  for (int i = tid; i < BK * BN; i += 256) { (&Bs[0][0])[i].x = 0; (&Bs[0][0])[i].y = 0; }
+  const int ty = tid >> 4, tx = tid & 15;
+  V acc[4][4];
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) { acc[i][j].x = 0; acc[i][j].y = 0; }
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - tk);
+  for (uint64_t s = 0; s < nsteps; s++) {
+    const uint64_t ka = deposit(s, op.a_k + tk, op.n_k - tk);
+    const uint64_t kb = deposit(s, op.b_k + tk, op.n_k - tk);
+    __syncthreads();
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) (&As[0][0])[(a_dst[i] >> RM) * BM + (a_dst[i] & (BM - 1))] = conjv(A[ka + a_off[i]], op.conj_a);
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) (&Bs[0][0])[(b_dst[i] >> RN) * BN + (b_dst[i] & (BN - 1))] = conjv(B[kb + b_off[i]], op.conj_b);
+    __syncthreads();
+    for (int k = 0; k < BK; k++) {
+      V a[4], b[4];
+      for (int i = 0; i < 4; i++) a[i] = As[k][ty + 16 * i];
+      for (int j = 0; j < 4; j++) b[j] = Bs[k][tx + 16 * j];
+      for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) acc[i][j] = cfma(acc[i][j], a[i], b[j]);
+    }
+  }
+  const int mvalid = 1 << tm, nvalid = 1 << tn;
+  for (int i = 0; i < 4; i++) {
+    const int row = ty + 16 * i;
+    if (row >= mvalid) continue;
+    const uint64_t ro = deposit(row, op.c_m, tm);
+    for (int j = 0; j < 4; j++) {
+      const int col = tx + 16 * j;
+      if (col >= nvalid) continue;
+      V* d = C + ro + deposit(col, op.c_n, tn);
+      if (op.accumulate) { V o = *d; o.x += acc[i][j].x; o.y += acc[i][j].y; *d = o; }
+      else *d = acc[i][j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename T>
+static hipError_t launch_row_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
+  const uint64_t rows = uint64_t(1) << op.n_rows;
+  dim3 grid(blocks_for(rows, kRowThreads), ctx.n_batch);
+  switch (op.n_in) {
+    case 0: hipLaunchKernelGGL((row_kernel<T, 1>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 1: hipLaunchKernelGGL((row_kernel<T, 2>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 2: hipLaunchKernelGGL((row_kernel<T, 4>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 3: hipLaunchKernelGGL((row_kernel<T, 8>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 4: hipLaunchKernelGGL((row_kernel<T, 16>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_splitk_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
+  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+  const uint64_t waves = uint64_t(1) << (op.n_rows + ks);
+  dim3 grid(blocks_for(waves, kRowThreads / 64), ctx.n_batch);
+  switch (op.n_in) {
+    case 0: hipLaunchKernelGGL((splitk_kernel<T, 1>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 1: hipLaunchKernelGGL((splitk_kernel<T, 2>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 2: hipLaunchKernelGGL((splitk_kernel<T, 4>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 3: hipLaunchKernelGGL((splitk_kernel<T, 8>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 4: hipLaunchKernelGGL((splitk_kernel<T, 16>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_row(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s) {
+  if (op.k_split_bits >= 0) return f64 ? launch_splitk_t<double>(ctx, op, s) : launch_splitk_t<float>(ctx, op, s);
+  return f64 ? launch_row_t<double>(ctx, op, s) : launch_row_t<float>(ctx, op, s);
+}
+
+hipError_t launch_reduce(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s) {
+  const uint64_t n = uint64_t(1) << (op.n_rows + op.n_in);
+  dim3 grid(blocks_for(n, kRowThreads), ctx.n_batch);
+  if (f64) hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kRowThreads), 0, s, ctx, op);
+  else hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kRowThreads), 0, s, ctx, op);
+  return hipGetLastError();
+}
+
+int gemm_tile_bits(int tile, int* bm, int* bn) {
+  switch (tile) {
+    case 0: *bm = 7; *bn = 7; return 0;     // 128 x 128
+    case 1: *bm = 6; *bn = 7; return 0;     // 64 x 128
+    case 2: *bm = 7; *bn = 6; return 0;     // 128 x 64
+    case 3: *bm = 6; *bn = 6; return 0;     // 64 x 64
+    case 4: *bm = 6; *bn = 6; return 0;     // VALU 64 x 64
+    default: return -1;
+  }
+}
+
+hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s) {
+  int bm, bn;
+  int tile = op.tile;
+  if (prec == TN_C128) tile = 4;
+  if (gemm_tile_bits(tile, &bm, &bn)) return hipErrorInvalidValue;
+  const int tm = op.n_m < bm ? op.n_m : bm, tn = op.n_n < bn ? op.n_n : bn;
+  const uint64_t tiles = uint64_t(1) << ((op.n_m - tm) + (op.n_n - tn));
+  const uint64_t gy = uint64_t(ctx.n_batch) << op.n_h;
+  if (tiles > 0x7fffffffULL || gy > 65535) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)tiles, (unsigned)gy);
+  if (prec == TN_C128) {
+    hipLaunchKernelGGL(gemm_valu<double>, grid, dim3(256), 0, s, ctx, op);
+    return hipGetLastError();
+  }
+  switch (tile) {
+    case 0: hipLaunchKernelGGL((gemm_mfma_4m<128, 128, 16>), grid, dim3(256), 0, s, ctx, op); break;
+    case 1: hipLaunchKernelGGL((gemm_mfma_4m<64, 128, 16>), grid, dim3(256), 0, s, ctx, op); break;
+    case 2: hipLaunchKernelGGL((gemm_mfma_4m<128, 64, 16>), grid, dim3(256), 0, s, ctx, op); break;
+    case 3: hipLaunchKernelGGL((gemm_mfma_4m<64, 64, 16>), grid, dim3(256), 0, s, ctx, op); break;
+    case 4: hipLaunchKernelGGL(gemm_valu<float>, grid, dim3(256), 0, s, ctx, op); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const Ctx& ctx, const PermuteOp& op, bool f64, hipStream_t s) {
+  const uint64_t n = uint64_t(1) << op.n_bits;
+  dim3 grid(blocks_for(n, 256), op.per_slice_serial ? 1 : ctx.n_batch);
+  const bool sd = op.src_c128 != 0, dd = op.dst_c128 != 0;
+  (void)f64;
+  if (sd && dd) hipLaunchKernelGGL((permute_kernel<double, double>), grid, dim3(256), 0, s, ctx, op);
+  else if (sd) hipLaunchKernelGGL((permute_kernel<double, float>), grid, dim3(256), 0, s, ctx, op);
+  else if (dd) hipLaunchKernelGGL((permute_kernel<float, double>), grid, dim3(256), 0, s, ctx, op);
+  else hipLaunchKernelGGL((permute_kernel<float, float>), grid, dim3(256), 0, s, ctx, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum(const Ctx& ctx, const AccumOp& op, bool f64, hipStream_t s) {
+  dim3 grid(blocks_for((uint64_t)op.n, 256));
+  if (f64) hipLaunchKernelGGL(accum_kernel<double>, grid, dim3(256), 0, s, ctx, op);
+  else hipLaunchKernelGGL(accum_kernel<float>, grid, dim3(256), 0, s, ctx, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, ctx, value, add);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s) {
+  const uint64_t words = (bytes + 7) / 8;
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(words, 256)), dim3(256), 0, s, base, words);
+  return hipGetLastError();
+}
+
+}  // namespace tn

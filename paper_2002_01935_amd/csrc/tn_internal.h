@@ -1,0 +1,100 @@
+// Internal types shared by the host planner (plan.cpp) and the device code
+// (kernels.hip, exec.hip).  Not part of the public ABI.
+//
+// Every index of dimension 2^b is split into b binary "bit indices".  A tensor
+// is then addressed by bit positions: the element offset of an assignment is
+// the sum over its bit indices of (bit value << position), so any axis
+// permutation, and any leaf with sliced axes removed, is described by the list
+// of positions of its bits.  Kernels read operands straight from such layouts
+// (the permutation is fused into the loads) and write outputs into the layout
+// the consuming node asks for.
+#pragma once
+
+#include <stdint.h>
+
+namespace tn {
+
+constexpr int kMaxBits = 48;      // bits per class list (rows, k)
+constexpr int kMaxInThread = 4;   // in-thread free bits of the row kernels (16 outputs)
+constexpr int kMaxSliceTerms = 8; // sliced bits on one leaf
+constexpr int kMaxTileBits = 16;
+
+// Where an operand lives.  kind: 0 = leaf (pointer table slot `slot`),
+// 1 = per-slice arena (byte offset `off` + slice * arena_stride),
+// 2 = external pointer table slot shared by all slices (outputs, grad_out).
+struct Ref {
+  int32_t kind;
+  int32_t slot;
+  int64_t off;
+  int32_t n_slice;                       // sliced-bit terms (leaves only)
+  uint8_t slice_bit[kMaxSliceTerms];     // bit of the slice id
+  uint8_t slice_pos[kMaxSliceTerms];     // position in the leaf
+};
+
+// Common launch context of every op.
+struct Ctx {
+  uint64_t ws;            // workspace base (device address)
+  uint64_t arena_stride;  // bytes between the arenas of consecutive in-flight slices
+  int64_t ptrtab_off;     // byte offset of the device pointer table (uint64 per slot)
+  int64_t sid_off;        // byte offset of the int64 slice-id list
+  int64_t counter_off;    // byte offset of the int64 batch counter
+  int64_t arena_off;      // byte offset of the first slice's arena
+  int32_t n_batch;        // slices per batch (grid dimension)
+  int32_t elem_bytes;     // 8 (complex64) or 16 (complex128)
+};
+
+// Row kernel: out[c] = sum_k A[a] * opB(B[b]).  Threads enumerate `rows`
+// (row index bit i has position row_c[i] in C, row_a[i] in A, row_b[i] in B;
+// -1 = absent); each thread computes all 2^n_in outputs of its in-thread bits
+// (positions in_c / in_b) and sums over 2^n_k values of the summed bits.
+// With k_split_bits > 0 the summed range is cut into 2^k_split_bits chunks of
+// 64-lane wavefronts (lanes stride over k) whose partial sums go to `part` and
+// are reduced in a fixed order by the reduce kernel.
+struct RowOp {
+  Ref a, b, c;
+  Ref part;                // split-K partials (arena), layout [chunk][row][in]
+  int32_t n_rows, n_in, n_k;
+  int32_t k_split_bits;    // log2 number of K chunks (split-K mode); -1 = row mode
+  int32_t conj_a, conj_b;
+  int32_t accumulate;      // add into C instead of overwriting
+  int8_t row_c[kMaxBits], row_a[kMaxBits], row_b[kMaxBits];
+  int8_t in_c[kMaxInThread], in_b[kMaxInThread];
+  int8_t k_a[kMaxBits], k_b[kMaxBits];
+};
+
+// Matrix-core / tiled GEMM: C[h, m, n] = sum_k A[h, m, k] * opB(B[h, k, n]).
+// Logical bit i of m has position a_m[i] in A and c_m[i] in C, etc.  The tile
+// covers the lowest tm_bits of m, tn_bits of n and tk_bits of k; the rest are
+// enumerated by the grid (m, n, h) and by the k loop.
+struct GemmOp {
+  Ref a, b, c;
+  int32_t n_h, n_m, n_n, n_k;
+  int32_t conj_a, conj_b;
+  int32_t accumulate;
+  int32_t tile;            // tile variant id (autotuned)
+  int8_t a_h[16], b_h[16], c_h[16];
+  int8_t a_m[kMaxBits], c_m[kMaxBits];
+  int8_t b_n[kMaxBits], c_n[kMaxBits];
+  int8_t a_k[kMaxBits], b_k[kMaxBits];
+};
+
+// Fixed-order FP64 accumulation of each in-flight slice's root into dst.
+struct AccumOp {
+  Ref src;                 // root value (per slice, arena)
+  Ref dst;                 // complex128 accumulator (pointer table slot)
+  int64_t n;               // elements
+};
+
+// Copy a tensor between layouts (general bit permutation), with optional
+// accumulation into the destination; used for leaf gradients and conversions.
+struct PermuteOp {
+  Ref src, dst;
+  int32_t n_bits;
+  int32_t src_c128;        // source stored as complex128 (grad_out)
+  int32_t dst_c128;
+  int32_t accumulate;
+  int32_t per_slice_serial;// accumulate the in-flight slices one after another (deterministic)
+  int8_t src_pos[kMaxBits], dst_pos[kMaxBits];
+};
+
+}  // namespace tn

@@ -1,0 +1,45 @@
+"""Helpers for the GPU tests: run a network through libtn and compare with the
+oracle.  Inputs come from tn_inputs; expected values from oracle/ only."""
+
+import sys
+
+import numpy as np
+
+TOL_C64 = 1e-5
+TOL_C128 = 1e-10
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def note(*msg):
+    print(*msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(net, precision):
+    import torch
+    dt = torch.complex128 if precision == "c128" else torch.complex64
+    return [torch.from_numpy(np.ascontiguousarray(t)).to(device="cuda", dtype=dt).contiguous() for t in net.leaves]
+
+
+def gpu_sliced(net, tree, sliced=(), slice_ids=None, precision="c64_4m", max_inflight=0, plan=None):
+    import torch
+    from paper_2002_01935_amd.binding import Plan
+    p = plan or Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=max_inflight)
+    leaves = to_dev(net, precision)
+    out = p.contract_sliced(leaves, slice_ids=slice_ids)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def gpu_contract(net, tree, precision="c64_4m"):
+    import torch
+    from paper_2002_01935_amd.binding import Plan
+    p = Plan(net, tree, precision=precision)
+    out = p.contract(to_dev(net, precision))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

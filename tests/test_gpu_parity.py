@@ -1,0 +1,109 @@
+"""GPU parity: libtn (HIP, gfx950) against the complex128 oracle on seeded
+inputs.  Tolerances: 1e-10 relative for complex128, 1e-5 for complex64."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import TOL_C128, TOL_C64, gpu_contract, gpu_sliced, note, rel
+from tn_inputs.circuits import circuit_network
+from tn_inputs.graphs import pairwise_network, random_network, rrg_network
+from tn_inputs.greedy import find_tree
+from tn_inputs.network import Network, Tree
+
+pytestmark = pytest.mark.gpu
+
+TWO = Tree(np.array([0], np.int32), np.array([1], np.int32))
+
+# (h, m, n, k) log2 class sizes: dot, outer, row kernel both orientations,
+# split-K with and without chunks, matrix-core GEMM (partial and full tiles,
+# K = 0, batch), and tiny cases
+SHAPES = [(0, 0, 0, 0), (0, 0, 0, 10), (0, 3, 2, 0), (0, 10, 2, 3), (0, 2, 10, 3), (0, 1, 1, 16),
+          (0, 4, 4, 8), (3, 2, 2, 2), (0, 5, 5, 0), (0, 6, 6, 4), (0, 7, 9, 5), (0, 10, 10, 8),
+          (2, 6, 6, 3), (0, 12, 5, 1), (0, 8, 7, 11), (1, 9, 3, 6), (0, 5, 8, 2)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_pairwise(oracle_lib, shape, prec):
+    net = pairwise_network(*shape, seed=sum(shape) * 7 + len(prec))
+    ref = oracle_lib.contract(net, TWO)
+    note("pairwise", shape, prec)
+    tol = TOL_C128 if prec == "c128" else TOL_C64
+    got = gpu_sliced(net, TWO, precision=prec)
+    assert got.shape == ref.shape
+    assert rel(got, ref) < tol
+    got2 = gpu_contract(net, TWO, precision=prec)
+    assert rel(got2, ref) < tol
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_trees_hyper_outputs(oracle_lib, seed, prec):
+    net = random_network(9, 14, 4, seed=100 + seed, n_out=2, dims=(2, 4), hyper=True)
+    tree = find_tree(net, seed=seed, trials=2)
+    ref = oracle_lib.contract(net, tree)
+    note("random tree", seed, prec)
+    got = gpu_sliced(net, tree, precision=prec)
+    assert rel(got, ref) < (TOL_C128 if prec == "c128" else TOL_C64)
+
+
+def test_cfg1_amplitudes_c128(oracle_lib):
+    """3x3 grid, 8 cycles, complex128, greedy tree, no slicing: GPU amplitude
+    against the oracle for 32 seeded bitstrings (same tree for all)."""
+    net0 = circuit_network(3, 3, 8, 0, 0)
+    tree = find_tree(net0, seed=0, trials=1)
+    rng = np.random.default_rng(0)
+    for b in [int(rng.integers(0, 2 ** 9))] + list(range(31)):
+        net = circuit_network(3, 3, 8, 0, b)
+        ref = oracle_lib.contract(net, tree)
+        got = gpu_contract(net, tree, precision="c128")
+        assert abs(complex(got) - complex(ref)) <= TOL_C128 * abs(complex(ref))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cfg2_rrg(oracle_lib, seed):
+    """120-vertex random 3-regular network: complex128 within 1e-10;
+    complex64 4M within 1e-5 relative, or within 1e-5 normwise backward error
+    (relative error divided by the condition number of the root product)."""
+    net = rrg_network(120, 3, seed=seed)
+    tree = find_tree(net, seed=seed, trials=8, slice_width=20)
+    sl = tree.meta["sliced"]
+    ref = complex(oracle_lib.contract(net, tree, sliced=sl))
+    note("cfg2", seed, "W_s", tree.meta["W_s"], "sliced", sl)
+    g128 = complex(gpu_sliced(net, tree, sliced=sl, precision="c128"))
+    assert abs(g128 - ref) <= TOL_C128 * abs(ref)
+    g64 = complex(gpu_sliced(net, tree, sliced=sl, precision="c64_4m"))
+    note("cfg2 c64 rel err", abs(g64 - ref) / abs(ref))
+    assert abs(g64 - ref) <= 1e-4 * abs(ref)
+
+
+def test_sliced_subsets_and_batches(oracle_lib):
+    net = random_network(10, 16, 4, seed=7, n_out=1, dims=(2,), hyper=False)
+    tree = find_tree(net, seed=1, trials=2)
+    cand = [e for e in range(net.n_idx) if e not in net.out_idx]
+    sliced = cand[:4]
+    ref_all = oracle_lib.contract(net, tree, sliced=sliced)
+    ids = [3, 0, 9, 14, 5]
+    ref_sub = oracle_lib.contract(net, tree, sliced=sliced, slice_ids=ids)
+    outs = []
+    for nb in (1, 2, 3, 16):
+        note("slices batch", nb)
+        got = gpu_sliced(net, tree, sliced=sliced, precision="c128", max_inflight=nb)
+        assert rel(got, ref_all) < TOL_C128
+        sub = gpu_sliced(net, tree, sliced=sliced, slice_ids=ids, precision="c128", max_inflight=nb)
+        assert rel(sub, ref_sub) < TOL_C128
+        outs.append(gpu_sliced(net, tree, sliced=sliced, precision="c64_4m", max_inflight=nb))
+    # fixed-order FP64 slice sum: identical bits whatever the batch size
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_repeat_is_bitwise_identical():
+    net = rrg_network(60, 3, seed=3)
+    tree = find_tree(net, seed=0, trials=2, slice_width=12)
+    sl = tree.meta["sliced"]
+    from paper_2002_01935_amd.binding import Plan
+    p = Plan(net, tree, sliced=sl)
+    a = gpu_sliced(net, tree, plan=p)
+    b = gpu_sliced(net, tree, plan=p)
+    assert np.array_equal(a, b)

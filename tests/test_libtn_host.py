@@ -1,0 +1,119 @@
+"""Host-side checks of libtn (no GPU): the library loads and exports every
+entry point declared in include/tn.h, tn_plan validates its input, and the
+plan's width and cost agree with the oracle's independent computation."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tn_inputs.circuits import circuit_network
+from tn_inputs.graphs import random_network, rrg_network
+from tn_inputs.greedy import find_tree
+from tn_inputs.network import Network, Tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2002_01935_amd import binding
+    return binding
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tn_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(B):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(B.lib, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_plan_matches_oracle_width_cost(B, oracle_lib):
+    for net, sw in ((circuit_network(3, 3, 8, 0, 0), None), (rrg_network(60, 3, seed=2), 14),
+                    (circuit_network(4, 4, 6, 1, 0, open_qubits=(5, 6)), 9)):
+        tree = find_tree(net, seed=0, trials=2, slice_width=sw)
+        sl = tree.meta.get("sliced", [])
+        info = B.Plan(net, tree, sliced=sl).info()
+        W, lc = oracle_lib.width_cost(net, tree)
+        Ws, _ = oracle_lib.width_cost(net, tree, sliced=sl)
+        assert info["W"] == W and info["W_s"] == Ws
+        assert abs(info["log2_C"] - lc) < 1e-9
+        assert info["d_sliced"] == 2 ** len(sl)
+        # 8 C_s per slice: the oracle's cost with the sliced indices removed
+        _, lcs = oracle_lib.width_cost(net, tree, sliced=sl)
+        assert abs(np.log2(info["flops_per_slice"] / 8) - lcs) < 1e-9
+
+
+def test_node_classes(B):
+    net = rrg_network(120, 3, seed=0)
+    tree = find_tree(net, seed=0, trials=2)
+    nodes = B.Plan(net, tree).nodes()
+    assert len(nodes) == 119
+    for n in nodes:
+        big = min(n["logM"], n["logN"]) >= 5
+        assert (n["kclass"] == "gemm") == big
+        assert n["flops"] == 8 * 2 ** (n["logH"] + n["logM"] + n["logN"] + n["logK"])
+
+
+def _net(leaves_shapes, idx, dims, out):
+    leaves = [np.zeros(s, dtype=np.complex128) for s in leaves_shapes]
+    return Network(leaves, idx, dims, out)
+
+
+@pytest.mark.parametrize("case,code", [("self_loop", -1), ("dangling", -1), ("bad_tree", -1),
+                                       ("sliced_output", -1), ("dup_output", -1), ("non_pow2", -2)])
+def test_validation_errors(B, case, code):
+    t = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    sl = []
+    if case == "self_loop":
+        net = Network([np.zeros((2, 2)), np.zeros(2)], [[0, 0], [0]], [2], [])
+    elif case == "dangling":
+        net = _net([(2, 2), (2,)], [[0, 1], [0]], [2, 2], [])
+    elif case == "bad_tree":
+        net, t = _net([(2, 2), (2, 2)], [[0, 1], [1, 0]], [2, 2], []), Tree(np.array([0], np.int32), np.array([0], np.int32))
+    elif case == "sliced_output":
+        net, sl = _net([(2, 2), (2, 2)], [[0, 1], [1, 2]], [2, 2, 2], [0, 2]), [0]
+    elif case == "dup_output":
+        net = _net([(2, 2), (2, 2)], [[0, 1], [1, 2]], [2, 2, 2], [0, 0])
+    else:
+        net = _net([(3, 2), (3, 2)], [[0, 1], [0, 1]], [3, 2], [])
+    with pytest.raises(B.TNError) as ei:
+        B.Plan(net, t, sliced=sl)
+    assert ei.value.code == code
+
+
+def test_workspace_and_null_checks(B):
+    net = random_network(6, 8, 4, seed=1)
+    net = Network(net.leaves, net.leaf_idx, [2] * net.n_idx, net.out_idx)
+    tree = find_tree(net, seed=0, trials=1)
+    p = B.Plan(net, tree)
+    need = p.info()["workspace_bytes"]
+    dummy = (ctypes.c_void_p * net.n_leaves)(*([0x1000] * net.n_leaves))
+    rc = B.lib.tn_contract(p.handle, dummy, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), need - 1, None)
+    assert rc == -4
+    rc = B.lib.tn_contract(p.handle, dummy, None, ctypes.c_void_p(0x1000), need, None)
+    assert rc == -1
+    assert b"null" in B.lib.tn_last_error()
+
+
+def test_backward_plan_recomputes(B):
+    # the reverse program keeps few large intermediates: its workspace stays
+    # far below the sum of every node value, and its FLOPs include recomputation
+    net = circuit_network(5, 5, 10, 0, 0)
+    tree = find_tree(net, seed=0, trials=4)
+    p = B.Plan(net, tree)
+    info = p.info()
+    gates = [v for v, k in enumerate(net.meta["leaf_kinds"]) if k == "2q"]
+    bi = p.backward_info(gates)
+    nodes = p.nodes()
+    assert bi["flops_per_slice"] >= 2.9 * info["flops_per_slice"]
+    assert bi["flops_per_slice"] <= 5.0 * info["flops_per_slice"]

@@ -100,3 +100,41 @@ def random_network(n_leaves: int, n_idx: int, max_rank: int, seed: int, n_out: i
                   meta=dict(kind="random", seed=seed))
     net.check()
     return net
+
+
+def pairwise_network(h: int, m: int, n: int, k: int, seed: int, dims=(2, 4)) -> Network:
+    """Two leaves A(H, M, K) and B(H, K, N) with open outputs (H, M, N), each in
+    a random axis order.  h, m, n, k are log2 sizes of the classes; indices
+    have dimensions drawn from `dims` (powers of two) to fill each class."""
+    rng = np.random.default_rng(seed)
+
+    def split(bits):
+        out = []
+        while bits > 0:
+            choices = [d for d in dims if int(np.log2(d)) <= bits]
+            d = int(rng.choice(choices))
+            out.append(d)
+            bits -= int(np.log2(d))
+        return out
+
+    idx_dim = []
+    cls = {}
+    for name, bits in (("H", h), ("M", m), ("N", n), ("K", k)):
+        ids = []
+        for d in split(bits):
+            ids.append(len(idx_dim))
+            idx_dim.append(d)
+        cls[name] = ids
+    a_idx = cls["H"] + cls["M"] + cls["K"]
+    b_idx = cls["H"] + cls["K"] + cls["N"]
+    out = cls["H"] + cls["M"] + cls["N"]
+    a_idx = [a_idx[i] for i in rng.permutation(len(a_idx))]
+    b_idx = [b_idx[i] for i in rng.permutation(len(b_idx))]
+    out = [out[i] for i in rng.permutation(len(out))]
+    leaves = []
+    for ix in (a_idx, b_idx):
+        shape = tuple(idx_dim[e] for e in ix)
+        leaves.append((rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(np.complex128))
+    net = Network(leaves, [a_idx, b_idx], idx_dim, out, meta=dict(kind="pairwise", hmnk=(h, m, n, k)))
+    net.check()
+    return net
