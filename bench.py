@@ -1,0 +1,306 @@
+#!/usr/bin/env python
+"""Throughput of sliced tensor-network contraction on one MI355X.
+
+Default workload: 54-qubit 6x9 grid circuit, 12 cycles, six open qubits (64
+correlated amplitudes), tree sliced to width 30 (2^30 complex64 = 8 GiB
+intermediates), complex64 with FP32 matrix cores (4M).  A step is one
+tn_contract_sliced call over `--slices-per-step` seeded slice ids (FP64 sum of
+their 64-amplitude roots); the whole hot path (plan, slice instantiation,
+permute-fused loads, vector-ALU and matrix-core contractions, FP64 slice
+accumulation, graph replay) runs in every step.
+
+Printed as one JSON line:
+  value       8 C_s / time over the timed steps (complex FLOPs, Sec. 2), TFLOP/s
+  roofline    dominant kernel (the GEMM launch with the largest total time):
+              algorithmic FLOPs of one launch / its average duration, timed
+              with HIP events around every launch over the same number of
+              steps, against the FP32 matrix-core peak (157.3 TFLOP/s)
+  cpu_baseline  the CPU oracle on one sub-slice of the same tree (more
+              indices sliced so that it runs in seconds), same FLOP convention
+  plain_fp64  the same tree and slice run node by node with materialised
+              permutes and complex128 matmuls in PyTorch (one slice)
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"c64_4m": 157.3, "c64_3m": 157.3, "c64_bf16x3": 2500.0, "c128": 78.6}
+WORKLOADS = {
+    "cfg5": "6x9 grid circuit (54 qubits), 12 cycles, fSim(pi/2,pi/6) + sqrtX/Y/W, 6 open qubits "
+            "(64 amplitudes), sliced to W_s=30, seeded slice ids",
+    "cfg3": "7x7 grid circuit (49 qubits), 14 cycles, one amplitude, sliced to W_s=27, seeded slice ids",
+    "cfg2": "random 3-regular graph, 120 rank-3 tensors, bond 2, sliced to W_s=20, all slices",
+    "cfg4": "6x6 grid circuit (36 qubits), 12 cycles, one amplitude, W=28, unsliced",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def permute_any(x, perm, torch):
+    """x.permute(perm).contiguous() for any rank: axes that stay adjacent are
+    merged first; if more than 16 groups remain (the limit of the copy kernel
+    in this PyTorch build), the permutation is applied as a sequence of
+    windowed permutes (odd-even block transposition on groups of 7)."""
+    shape = list(x.shape)
+    target = list(perm)
+    while True:
+        # merge source axes that are adjacent and in order in the target
+        groups = []
+        for a in target:
+            if groups and groups[-1][-1] + 1 == a:
+                groups[-1].append(a)
+            else:
+                groups.append([a])
+        order = sorted(range(len(groups)), key=lambda g: groups[g][0])   # source order of groups
+        sizes = {g: int(math.prod(shape[a] for a in groups[g])) for g in range(len(groups))}
+        y = x.reshape([sizes[g] for g in order])
+        rank_in_target = {g: i for i, g in enumerate(range(len(groups)))}
+        src_pos = {g: i for i, g in enumerate(order)}
+        if len(groups) <= 16:
+            return y.permute(*[src_pos[g] for g in range(len(groups))]).contiguous().reshape(
+                [shape[a] for a in target])
+        # one pass: sort windows of 14 consecutive source groups by target rank
+        cur = list(order)
+        for start in (0, 7):
+            new = []
+            i = 0
+            while i < len(cur):
+                if i >= start and (i - start) % 14 == 0:
+                    new.extend(sorted(cur[i:i + 14], key=lambda g: rank_in_target[g]))
+                    i += 14
+                elif i < start:
+                    new.append(cur[i])
+                    i += 1
+                else:
+                    new.append(cur[i])
+                    i += 1
+            cur = new
+            pre_dims = []
+            # apply this window pass as permutes of at most 16 dims each
+            yy = y
+            i = 0
+            dims = [sizes[g] for g in order]
+            for w0 in range(start, len(order), 14):
+                w1 = min(w0 + 14, len(order))
+                win = order[w0:w1]
+                want = sorted(win, key=lambda g: rank_in_target[g])
+                lead = int(math.prod(dims[:w0])) if w0 else 1
+                tail = int(math.prod(dims[w1:])) if w1 < len(order) else 1
+                yy = yy.reshape([lead] + dims[w0:w1] + [tail])
+                p = [0] + [1 + win.index(g) for g in want] + [len(win) + 1]
+                yy = yy.permute(*p).contiguous()
+                dims = dims[:w0] + [sizes[g] for g in want] + dims[w1:]
+                order = order[:w0] + want + order[w1:]
+                yy = yy.reshape(dims)
+            y = yy
+        # continue with the partially sorted tensor: its axes are now `order`
+        x = y.reshape([shape[a] for g in order for a in groups[g]])
+        shape = [shape[a] for g in order for a in groups[g]]
+        flat = [a for g in order for a in groups[g]]
+        target = [flat.index(a) for a in target]
+
+
+def plain_fp64(net, tree, sliced, slice_id, torch):
+    """Node-by-node complex128 contraction with materialised permutes and
+    torch.matmul (the per-contraction baseline); returns (value, seconds)."""
+    import numpy as np
+    dev = "cuda"
+    n = net.n_leaves
+    # slice values: mixed radix, first sliced index most significant
+    val = {}
+    sid = slice_id
+    for e in reversed(list(sliced)):
+        val[e] = sid % net.idx_dim[e]
+        sid //= net.idx_dim[e]
+    leaves = []
+    for t, ix in zip(net.leaves, net.leaf_idx):
+        x = torch.from_numpy(np.ascontiguousarray(t)).to(dev, torch.complex128)
+        keep = []
+        for a, e in enumerate(ix):
+            if e in val:
+                x = x.select(len(keep), int(val[e]))
+            else:
+                keep.append(e)
+        leaves.append((x.contiguous(), keep))
+    total = {}
+    for ix in net.leaf_idx:
+        for e in ix:
+            total[e] = total.get(e, 0) + 1
+    outs = set(net.out_idx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vals = dict(enumerate(leaves))
+    count = {v: {e: 1 for e in ix} for v, ix in enumerate(net.leaf_idx)}
+    for k, (l, r) in enumerate(zip(tree.left, tree.right)):
+        (A, ia), (B, ib) = vals.pop(int(l)), vals.pop(int(r))
+        cl, cr = count.pop(int(l)), count.pop(int(r))
+        c = dict(cl)
+        for e, x in cr.items():
+            c[e] = c.get(e, 0) + x
+        kept = [e for e in ia + [e for e in ib if e not in ia] if e not in val and (e in outs or c[e] < total[e])]
+        summed = [e for e in ia if e in ib and e not in kept]
+        batch = [e for e in kept if e in ia and e in ib]
+        ma = [e for e in ia if e not in ib]
+        nb = [e for e in ib if e not in ia]
+        d = lambda es: int(math.prod(net.idx_dim[e] for e in es))  # noqa: E731
+        Ap = permute_any(A, [ia.index(e) for e in batch + ma + summed], torch).reshape(d(batch), d(ma), d(summed))
+        Bp = permute_any(B, [ib.index(e) for e in batch + summed + nb], torch).reshape(d(batch), d(summed), d(nb))
+        Cm = torch.matmul(Ap, Bp)
+        order = batch + ma + nb
+        Cm = Cm.reshape([net.idx_dim[e] for e in order]) if order else Cm.reshape(())
+        vals[n + k] = (Cm, order)
+        count[n + k] = {e: c[e] for e in order}
+    (R, ir), = vals.values()
+    R = permute_any(R, [ir.index(e) for e in net.out_idx], torch) if net.out_idx else R
+    torch.cuda.synchronize()
+    return R.cpu().numpy(), time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="c64_4m", choices=sorted(PEAK))
+    ap.add_argument("--slices-per-step", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-timed-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the sliced contraction is measured on a single MI355X "
+              "(slices would shard across GPUs with one all-reduce of the result; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    from tn_inputs import configs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    net, tree, sliced = configs.load(args.workload)
+    plan = Plan(net, tree, sliced=sliced, precision=args.precision, max_inflight_slices=1)
+    info = plan.info()
+    ids_all = configs.slice_subset(info["d_sliced"], seed=0, size=256)
+    B = max(1, min(args.slices_per_step, len(ids_all)))
+    log(f"workload {args.workload}: W={info['W']} W_s={info['W_s']} d_sliced={info['d_sliced']} "
+        f"8C/slice={info['flops_per_slice']:.3e} workspace={info['workspace_bytes'] / 2**30:.1f} GiB")
+    ws = plan.workspace()
+    dt = plan.storage_dtype
+    leaves = [torch.from_numpy(np.ascontiguousarray(t)).to("cuda", dt) for t in net.leaves]
+    out = torch.empty(plan.out_shape, dtype=torch.complex128, device="cuda")
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        plan.tune(ws)
+        log(f"autotune {time.perf_counter() - t0:.1f} s")
+
+    def step_ids(s):
+        return [ids_all[(s * B + j) % len(ids_all)] for j in range(B)]
+
+    for w in range(args.warmup):
+        plan.contract_sliced(leaves, slice_ids=step_ids(w), out=out, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {w} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        plan.contract_sliced(leaves, slice_ids=step_ids(args.warmup + s), out=out, workspace=ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    n_slices = args.steps * B
+    flops = info["flops_per_slice"] * n_slices
+    tflops = flops / elapsed / 1e12
+    per_slice = elapsed / n_slices
+    n_amps = int(np.prod(plan.out_shape)) if plan.out_shape else 1
+
+    roof = None
+    if not args.no_timed_pass:
+        agg = {}
+        for s in range(args.steps):
+            _, ops = plan.contract_sliced_timed(leaves, slice_ids=step_ids(args.warmup + s), out=out, workspace=ws)
+            for i, o in enumerate(ops):
+                a = agg.setdefault(i, dict(o, ms=0.0, launches=0))
+                a["ms"] += o["ms"]
+                a["launches"] += B
+        total_ms = sum(a["ms"] for a in agg.values())
+        by_kind = {}
+        for a in agg.values():
+            by_kind[a["kind"]] = by_kind.get(a["kind"], 0.0) + a["ms"]
+        gemms = [a for a in agg.values() if a["kind"] == "gemm"]
+        dom = max(gemms, key=lambda a: a["ms"])
+        avg_s = dom["ms"] / 1e3 / dom["launches"]
+        achieved = dom["flops"] / avg_s / 1e12
+        peak = PEAK[args.precision]
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "gemm_mfma_4m" if args.precision == "c64_4m" else args.precision,
+                "node": dom["node"], "flops_per_launch": dom["flops"], "avg_launch_ms": round(avg_s * 1e3, 3),
+                "time_share": round(dom["ms"] / total_ms, 4),
+                "time_by_kernel_class": {k: round(v / total_ms, 4) for k, v in sorted(by_kind.items())}}
+        log(f"dominant gemm node {dom['node']}: {avg_s * 1e3:.2f} ms/launch, {achieved:.1f} TFLOP/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import contract as oc
+        from tn_inputs.slicing import extend_slices
+        target = 37.0
+        ext = extend_slices(net, tree, sliced, target)
+        _, lc = oc.width_cost(net, tree, sliced=ext)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oc.contract(net, tree, sliced=ext, slice_ids=[0], n_threads=threads)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(8 * 2 ** lc / tc / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+               "sample": f"one sub-slice of the same tree with {len(ext) - len(sliced)} extra sliced indices "
+                         f"(8C = {8 * 2 ** lc:.3e} complex FLOPs) in {tc:.1f} s, complex128 loop nest"}
+        log(f"cpu oracle: {cpu['value'] * 1e3:.3f} GFLOP/s on {threads} threads ({tc:.1f} s)")
+
+    plain = None
+    if not args.no_plain:
+        try:
+            ref, tp = plain_fp64(net, tree, sliced, ids_all[0], torch)
+            plan1 = plan.contract_sliced(leaves, slice_ids=[ids_all[0]], out=out, workspace=ws).cpu().numpy()
+            err = float(np.linalg.norm(plan1 - ref) / np.linalg.norm(ref))
+            plain = {"s_per_slice": round(tp, 4), "speedup": round(tp / per_slice, 2),
+                     "rel_err_c64_vs_fp64_plain": err}
+            log(f"plain fp64 path: {tp:.2f} s/slice, speedup {tp / per_slice:.1f}x, rel err {err:.2e}")
+            del ref
+        except torch.cuda.OutOfMemoryError as e:   # the plain path materialises every permute
+            plain = {"error": f"out of memory: {e}"[:200]}
+        torch.cuda.empty_cache()
+
+    res = {
+        "metric": "TFLOP/s on contraction tree + s/amplitude at stated error vs FP64, vs plain path",
+        "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64" if args.precision != "c128" else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "precision": args.precision,
+                   "slices_per_step": B, "d_sliced": info["d_sliced"], "W": info["W"], "W_s": info["W_s"],
+                   "flops_8C_per_slice": info["flops_per_slice"], "amplitudes": n_amps},
+        "s_per_slice": round(per_slice, 4),
+        "s_per_amplitude_extrapolated": round(per_slice * info["d_sliced"] / n_amps, 4),
+        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

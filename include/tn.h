@@ -180,6 +180,23 @@ int tn_contract_backward(tn_plan_t plan, const void* const* leaves,
                          int64_t n_ids, const int64_t* slice_ids,
                          void* workspace, uint64_t workspace_bytes, void* stream);
 
+/*
+ * Same result as tn_contract_sliced, but the program runs op by op (no
+ * graph) with a HIP event recorded on `stream` before and after every kernel
+ * launch, and the call waits for the GPU.  For measurement: on return,
+ * n_ops receives the number of ops of one batch's program and, for i <
+ * min(n_ops, cap), op_ms[i] the summed duration of op i over all batches,
+ * op_kind[i] its kernel (0 row, 1 split-K, 2 split-K reduce, 3 GEMM,
+ * 4 FP64 accumulation, 5 permute, 6 batch counter), op_node[i] its tree node
+ * (-1 if none), op_flops[i] / op_bytes[i] its algorithmic complex FLOPs and
+ * bytes per in-flight slice.  Any output array may be NULL.
+ */
+int tn_contract_sliced_timed(tn_plan_t plan, const void* const* leaves, int64_t n_ids,
+                             const int64_t* slice_ids, void* out_c128, void* workspace,
+                             uint64_t workspace_bytes, void* stream, int32_t cap, float* op_ms,
+                             int32_t* op_kind, int32_t* op_node, double* op_flops,
+                             double* op_bytes, int32_t* n_ops);
+
 void tn_plan_destroy(tn_plan_t plan);
 
 /* Message for the last failing call on this thread ("" if none). */

@@ -23,8 +23,9 @@ KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm"}
 EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
-    "tn_last_error",
+    "tn_last_error", "tn_contract_sliced_timed",
 ]
+OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
 
 
 class TNError(RuntimeError):
@@ -53,6 +54,7 @@ def _load():
     lib.tn_contract.argtypes = [P, P, P, P, u64, P]
     lib.tn_contract_sliced.argtypes = [P, P, i64, P, P, P, u64, P]
     lib.tn_contract_backward.argtypes = [P, P, P, i32, P, P, i64, P, P, u64, P]
+    lib.tn_contract_sliced_timed.argtypes = [P, P, i64, P, P, P, u64, P, i32, P, P, P, P, P, P]
     lib.tn_plan_destroy.argtypes = [P]
     lib.tn_plan_destroy.restype = None
     lib.tn_last_error.restype = ctypes.c_char_p
@@ -203,6 +205,34 @@ class Plan:
         _check(lib.tn_contract_sliced(self.handle, _dev_ptrs(leaves), n, ptr, ctypes.c_void_p(out.data_ptr()),
                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
         return out
+
+    def contract_sliced_timed(self, leaves, slice_ids=None, out=None, workspace=None, stream=None):
+        """tn_contract_sliced run op by op with HIP events around every launch;
+        returns (out, [dict(kind, node, ms, flops, bytes) per op])."""
+        torch = self._check_leaves(leaves)
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=torch.complex128, device="cuda")
+        if workspace is None:
+            workspace = self.workspace()
+        if slice_ids is None:
+            n, ptr, keep = 0, None, None
+        else:
+            keep, ptr = _arr(list(slice_ids), np.int64)
+            n = len(keep)
+        cap = 1 << 16
+        ms = np.zeros(cap, np.float32)
+        kind = np.zeros(cap, np.int32)
+        node = np.zeros(cap, np.int32)
+        fl = np.zeros(cap, np.float64)
+        by = np.zeros(cap, np.float64)
+        nops = ctypes.c_int32()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib.tn_contract_sliced_timed(self.handle, _dev_ptrs(leaves), n, ptr, ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream),
+                                            cap, vp(ms), vp(kind), vp(node), vp(fl), vp(by), ctypes.byref(nops)))
+        ops = [dict(kind=OP_KINDS.get(int(kind[i]), "?"), node=int(node[i]), ms=float(ms[i]), flops=float(fl[i]),
+                    bytes=float(by[i])) for i in range(min(nops.value, cap))]
+        return out, ops
 
     def backward(self, leaves, grad_out, wrt, grads=None, slice_ids=None, workspace=None, stream=None):
         torch = self._check_leaves(leaves)

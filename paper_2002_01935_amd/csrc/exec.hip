@@ -362,6 +362,74 @@ extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_
   return run_batches(p, 1, forward_program(p, 1), ctx, (int64_t)ids.size() / p->n_batch, s);
 }
 
+static int op_kind_code(const Op& op) {
+  switch (op.kind) {
+    case OpKind::Row: return op.row.k_split_bits >= 0 ? 1 : 0;
+    case OpKind::RowReduce: return 2;
+    case OpKind::Gemm: return 3;
+    case OpKind::Accum: return 4;
+    case OpKind::Permute: return 5;
+    case OpKind::Counter: return 6;
+    default: return -1;
+  }
+}
+
+extern "C" int tn_contract_sliced_timed(tn_plan_t p, const void* const* leaves, int64_t n_ids,
+                                        const int64_t* slice_ids, void* out_c128, void* workspace,
+                                        uint64_t workspace_bytes, void* stream, int32_t cap, float* op_ms,
+                                        int32_t* op_kind, int32_t* op_node, double* op_flops, double* op_bytes,
+                                        int32_t* n_ops) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  if (!out_c128) return set_err(TN_E_INVALID, "output is null");
+  int rc = check_leaves(p, leaves);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < p->workspace_bytes)
+    return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->workspace_bytes) + " bytes required");
+  std::vector<int64_t> ids;
+  rc = make_ids(p, n_ids, slice_ids, ids);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = upload(p, workspace, leaves, out_c128, nullptr, nullptr, 0, ids, s);
+  if (rc) return rc;
+  const int64_t out_elems = int64_t(1) << (p->n_leaves > 1 ? p->kept_bits[2 * p->n_leaves - 2].size()
+                                                           : p->layout[0].bits.size());
+  HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(out_c128), (uint64_t)out_elems * 16, s));
+  Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
+  std::vector<Op> prog = forward_program(p, 1);
+  const size_t nop = prog.size();
+  const int64_t nbatches = (int64_t)ids.size() / p->n_batch;
+  std::vector<hipEvent_t> ev(nop + 1, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  std::vector<double> acc(nop, 0.0);
+  int result = TN_OK;
+  for (int64_t b = 0; b < nbatches && result == TN_OK; b++) {
+    if (hipEventRecord(ev[0], s) != hipSuccess) { result = set_err(TN_E_DEVICE, "hipEventRecord"); break; }
+    for (size_t i = 0; i < nop; i++) {
+      hipError_t e = launch_op(p, ctx, prog[i], s);
+      if (e == hipSuccess) e = hipEventRecord(ev[i + 1], s);
+      if (e != hipSuccess) { result = set_err(TN_E_DEVICE, std::string("timed launch: ") + hipGetErrorString(e)); break; }
+    }
+    if (result != TN_OK) break;
+    if (hipEventSynchronize(ev[nop]) != hipSuccess) { result = set_err(TN_E_DEVICE, "hipEventSynchronize"); break; }
+    for (size_t i = 0; i < nop; i++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc[i] += ms;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (result != TN_OK) return result;
+  if (n_ops) *n_ops = (int32_t)nop;
+  for (size_t i = 0; i < nop && (int32_t)i < cap; i++) {
+    if (op_ms) op_ms[i] = (float)acc[i];
+    if (op_kind) op_kind[i] = op_kind_code(prog[i]);
+    if (op_node) op_node[i] = prog[i].node;
+    if (op_flops) op_flops[i] = prog[i].flops;
+    if (op_bytes) op_bytes[i] = prog[i].bytes;
+  }
+  return TN_OK;
+}
+
 extern "C" int tn_contract(tn_plan_t p, const void* const* leaves, void* out, void* workspace,
                            uint64_t workspace_bytes, void* stream) {
   g_err.clear();
@@ -448,10 +516,13 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     if (it != best.end()) { g.tile = it->second; continue; }
     float best_ms = 1e30f;
     int best_tile = 0;
-    for (int t = 0; t < kNumGemmTiles; t++) {
+    // matrix-core tiles only; the summed range is cut to at most 2^9 values
+    // for the trials (time per tile scales with K, the ranking does not)
+    for (int t = 0; t < kNumGemmTiles - 1; t++) {
       GemmOp trial = g;
       trial.tile = t;
-      const int reps = 3;
+      trial.n_k = std::min(trial.n_k, 9);
+      const int reps = 2;
       HIP_TRY(launch_gemm(ctx, trial, p->prec, s));   // warm-up
       HIP_TRY(hipEventRecord(e0, s));
       for (int r = 0; r < reps; r++) HIP_TRY(launch_gemm(ctx, trial, p->prec, s));

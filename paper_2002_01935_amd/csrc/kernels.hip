@@ -29,11 +29,43 @@
 
 namespace tn {
 
+// Operand pointers are built from integer addresses (workspace offsets and a
+// device pointer table); tagging them with the global address space makes the
+// compiler emit global (not flat) loads and stores, whose completion counters
+// are independent of LDS traffic, so prefetches overlap computation.
+#define GMEM __attribute__((address_space(1)))
+
 // ------------------------------------------------------------------ helpers
 
 template <typename T> struct C2;
 template <> struct C2<float> { using t = float2; };
 template <> struct C2<double> { using t = double2; };
+
+template <typename V> struct Scal;
+template <> struct Scal<float2> { using t = float; };
+template <> struct Scal<double2> { using t = double; };
+
+// element load / store through the native two-lane vector type
+template <typename V>
+__device__ __forceinline__ V ld(GMEM const V* p) {
+  typedef typename Scal<V>::t T;
+  typedef T n2 __attribute__((ext_vector_type(2)));
+  const n2 v = *reinterpret_cast<GMEM const n2*>(p);
+  V r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+template <typename V>
+__device__ __forceinline__ void st(GMEM V* p, V v) {
+  typedef typename Scal<V>::t T;
+  typedef T n2 __attribute__((ext_vector_type(2)));
+  n2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *reinterpret_cast<GMEM n2*>(p) = w;
+}
 
 template <typename V>
 __device__ __forceinline__ V cmul(V a, V b) {
@@ -72,14 +104,14 @@ __device__ __forceinline__ int64_t slice_id(const Ctx& ctx, int z) {
 }
 
 // Base address of an operand for in-flight slice z with slice id sid.
-__device__ __forceinline__ char* resolve(const Ctx& ctx, const Ref& r, int z, int64_t sid, int ebytes) {
+__device__ __forceinline__ GMEM char* resolve(const Ctx& ctx, const Ref& r, int z, int64_t sid, int ebytes) {
   if (r.kind == 1)
-    return reinterpret_cast<char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
+    return reinterpret_cast<GMEM char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
   const uint64_t p = reinterpret_cast<const uint64_t*>(ctx.ws + ctx.ptrtab_off)[r.slot];
   uint64_t off = 0;
   for (int i = 0; i < r.n_slice; i++)
     if ((sid >> r.slice_bit[i]) & 1) off |= uint64_t(1) << r.slice_pos[i];
-  return reinterpret_cast<char*>(p) + off * uint64_t(ebytes);
+  return reinterpret_cast<GMEM char*>(p) + off * uint64_t(ebytes);
 }
 
 template <typename V>
@@ -110,9 +142,9 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
   const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (row >> op.n_rows) return;
   const int eb = sizeof(V);
-  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb));
-  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb));
-  V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
   const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
   const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
   const uint64_t oc = deposit(row, op.row_c, op.n_rows);
@@ -130,21 +162,21 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
       hia = deposit(k >> klo, op.k_a + klo, op.n_k - klo);
       hib = deposit(k >> klo, op.k_b + klo, op.n_k - klo);
     }
-    const V a = conjv(A[oa + hia + ktab_a[k & lomask]], op.conj_a);
+    const V a = conjv(ld(A + oa + hia + ktab_a[k & lomask]), op.conj_a);
     const uint64_t bb = ob + hib + ktab_b[k & lomask];
 #pragma unroll
-    for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a, conjv(B[bb + inb[j]], op.conj_b));
+    for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a, conjv(ld(B + bb + inb[j]), op.conj_b));
   }
 #pragma unroll
   for (int j = 0; j < NIN; j++) {
     const uint64_t c = oc + deposit(j, op.in_c, op.n_in);
     if (op.accumulate) {
-      V o = Cp[c];
+      V o = ld(Cp + c);
       o.x += acc[j].x;
       o.y += acc[j].y;
-      Cp[c] = o;
+      st(Cp + c, o);
     } else {
-      Cp[c] = acc[j];
+      st(Cp + c, acc[j]);
     }
   }
 }
@@ -180,8 +212,8 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
   const uint64_t chunk = wave & ((uint64_t(1) << ks) - 1);
   if (row >> op.n_rows) return;
   const int eb = sizeof(V);
-  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb));
-  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb));
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
   const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
   const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
   uint64_t inb[NIN];
@@ -203,11 +235,11 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
       hia = deposit(hi, op.k_a + klo, op.n_k - klo);
       hib = deposit(hi, op.k_b + klo, op.n_k - klo);
     }
-    const V a = conjv(A[oa + hia + ktab_a[k & lomask]], op.conj_a);
+    const V a = conjv(ld(A + oa + hia + ktab_a[k & lomask]), op.conj_a);
     const uint64_t bb = ob + hib + ktab_b[k & lomask];
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
-      const V b = conjv(B[bb + inb[j]], op.conj_b);
+      const V b = conjv(ld(B + bb + inb[j]), op.conj_b);
       ar[j] += a.x * b.x - a.y * b.y;
       ai[j] += a.x * b.y + a.y * b.x;
     }
@@ -216,7 +248,7 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
   for (int j = 0; j < NIN; j++) { ar[j] = wave_sum(ar[j]); ai[j] = wave_sum(ai[j]); }
   if (lane != 0) return;
   if (ks == 0) {
-    V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+    GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
     const uint64_t oc = deposit(row, op.row_c, op.n_rows);
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
@@ -224,18 +256,18 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
       V o;
       o.x = ar[j];
       o.y = ai[j];
-      if (op.accumulate) { V p = Cp[c]; o.x += p.x; o.y += p.y; }
-      Cp[c] = o;
+      if (op.accumulate) { V p = ld(Cp + c); o.x += p.x; o.y += p.y; }
+      st(Cp + c, o);
     }
   } else {
-    V* P = reinterpret_cast<V*>(resolve(ctx, op.part, z, sid, eb));
+    GMEM V* P = reinterpret_cast<GMEM V*>(resolve(ctx, op.part, z, sid, eb));
     const uint64_t base = ((chunk << op.n_rows) + row) * NIN;
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
       V o;
       o.x = ar[j];
       o.y = ai[j];
-      P[base + j] = o;
+      st(P + base + j, o);
     }
   }
 }
@@ -252,20 +284,20 @@ __global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) 
   const int j = (int)(t % nin);
   if (row >> op.n_rows) return;
   const int eb = sizeof(V);
-  const V* P = reinterpret_cast<const V*>(resolve(ctx, op.part, z, sid, eb));
-  V* Cp = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb));
+  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, eb));
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
   V s;
   s.x = 0;
   s.y = 0;
   const uint64_t nch = uint64_t(1) << op.k_split_bits;
   for (uint64_t ch = 0; ch < nch; ch++) {
-    const V p = P[((ch << op.n_rows) + row) * nin + j];
+    const V p = ld(P + ((ch << op.n_rows) + row) * nin + j);
     s.x += p.x;
     s.y += p.y;
   }
   const uint64_t c = deposit(row, op.row_c, op.n_rows) + deposit(j, op.in_c, op.n_in);
-  if (op.accumulate) { V p = Cp[c]; s.x += p.x; s.y += p.y; }
-  Cp[c] = s;
+  if (op.accumulate) { V p = ld(Cp + c); s.x += p.x; s.y += p.y; }
+  st(Cp + c, s);
 }
 
 // ------------------------------------------------------------------ permute / accumulate
@@ -283,19 +315,19 @@ __global__ __launch_bounds__(256) void permute_kernel(Ctx ctx, PermuteOp op) {
   for (int z = z0; z < z1; z++) {
     const int64_t sid = slice_id(ctx, z);
     if (sid < 0) continue;
-    const VS* S = reinterpret_cast<const VS*>(resolve(ctx, op.src, z, sid, sizeof(VS)));
-    VD* D = reinterpret_cast<VD*>(resolve(ctx, op.dst, z, sid, sizeof(VD)));
-    const VS s = S[so];
+    GMEM const VS* S = reinterpret_cast<GMEM const VS*>(resolve(ctx, op.src, z, sid, sizeof(VS)));
+    GMEM VD* D = reinterpret_cast<GMEM VD*>(resolve(ctx, op.dst, z, sid, sizeof(VD)));
+    const VS s = ld(S + so);
     VD d;
     if (op.accumulate) {
-      d = D[dof];
+      d = ld(D + dof);
       d.x += (TD)s.x;
       d.y += (TD)s.y;
     } else {
       d.x = (TD)s.x;
       d.y = (TD)s.y;
     }
-    D[dof] = d;
+    st(D + dof, d);
   }
 }
 
@@ -306,17 +338,17 @@ __global__ __launch_bounds__(256) void accum_kernel(Ctx ctx, AccumOp op) {
   using V = typename C2<T>::t;
   const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (o >= op.n) return;
-  double2* D = reinterpret_cast<double2*>(resolve(ctx, op.dst, 0, 0, 16));
-  double2 d = D[o];
+  GMEM double2* D = reinterpret_cast<GMEM double2*>(resolve(ctx, op.dst, 0, 0, 16));
+  double2 d = ld(D + o);
   for (int z = 0; z < ctx.n_batch; z++) {
     const int64_t sid = slice_id(ctx, z);
     if (sid < 0) continue;
-    const V* S = reinterpret_cast<const V*>(resolve(ctx, op.src, z, sid, sizeof(V)));
-    const V s = S[o];
+    GMEM const V* S = reinterpret_cast<GMEM const V*>(resolve(ctx, op.src, z, sid, sizeof(V)));
+    const V s = ld(S + o);
     d.x += (double)s.x;
     d.y += (double)s.y;
   }
-  D[o] = d;
+  st(D + o, d);
 }
 
 __global__ void counter_kernel(Ctx ctx, int64_t value, int add) {
@@ -393,12 +425,12 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
   const uint64_t tile_m = bid / ntiles_n, tile_n = bid % ntiles_n;
 
-  const char* Ab = resolve(ctx, op.a, z, sid, 8);
-  const char* Bb = resolve(ctx, op.b, z, sid, 8);
-  char* Cb = resolve(ctx, op.c, z, sid, 8);
-  const float2* A = reinterpret_cast<const float2*>(Ab) + deposit(h, op.a_h, op.n_h) +
+  GMEM const char* Ab = resolve(ctx, op.a, z, sid, 8);
+  GMEM const char* Bb = resolve(ctx, op.b, z, sid, 8);
+  GMEM char* Cb = resolve(ctx, op.c, z, sid, 8);
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(Ab) + deposit(h, op.a_h, op.n_h) +
                     deposit(tile_m, op.a_m + tm, op.n_m - tm);
-  const float2* B = reinterpret_cast<const float2*>(Bb) + deposit(h, op.b_h, op.n_h) +
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(Bb) + deposit(h, op.b_h, op.n_h) +
                     deposit(tile_n, op.b_n + tn, op.n_n - tn);
 
   // per-thread load slots: offset in the operand and place in the tile
@@ -416,7 +448,7 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
     bool ok = (e >> ma.nbits) == 0;
     for (int b = 0; b < ma.nbits; b++)
       if ((e >> b) & 1) { off |= 1u << ma.pos[b]; d |= 1 << ma.dst[b]; }
-    a_off[i] = off;
+    a_off[i] = ok ? off : 0u;
     a_dst[i] = ok ? (int16_t)d : (int16_t)-1;
   }
 #pragma unroll
@@ -427,7 +459,7 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
     bool ok = (e >> mb.nbits) == 0;
     for (int b = 0; b < mb.nbits; b++)
       if ((e >> b) & 1) { off |= 1u << mb.pos[b]; d |= 1 << mb.dst[b]; }
-    b_off[i] = off;
+    b_off[i] = ok ? off : 0u;
     b_dst[i] = ok ? (int16_t)d : (int16_t)-1;
   }
   // zero both buffers once (covers partial tiles)
@@ -441,11 +473,9 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
     const uint64_t ka = deposit(step, op.a_k + tk, op.n_k - tk);
     const uint64_t kb = deposit(step, op.b_k + tk, op.n_k - tk);
 #pragma unroll
-    for (int i = 0; i < LA; i++)
-      if (a_dst[i] >= 0) ra[i] = A[ka + a_off[i]];
+    for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
 #pragma unroll
-    for (int i = 0; i < LB; i++)
-      if (b_dst[i] >= 0) rb[i] = B[kb + b_off[i]];
+    for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -503,7 +533,7 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
   }
 
   // epilogue: C[row, col] at deposit(row, c_m) + deposit(col, c_n) (+ batch)
-  float* C = reinterpret_cast<float*>(Cb);
+  GMEM float* C = reinterpret_cast<GMEM float*>(Cb);
   const uint64_t cbase = deposit(h, op.c_h, op.n_h) + deposit(tile_m, op.c_m + tm, op.n_m - tm) +
                          deposit(tile_n, op.c_n + tn, op.n_n - tn);
   uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
@@ -524,7 +554,7 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
       for (int r = 0; r < 16; r++) {
         const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
         if (row >= mvalid) continue;
-        float* dst = C + 2 * (cbase + rowoff[row] + co) + bpar;
+        GMEM float* dst = C + 2 * (cbase + rowoff[row] + co) + bpar;
         if (op.accumulate) *dst += acc[i][j][r];
         else *dst = acc[i][j][r];
       }
@@ -553,11 +583,11 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
   const uint64_t tile_m = blockIdx.x / ntiles_n, tile_n = blockIdx.x % ntiles_n;
   const int eb = sizeof(V);
-  const V* A = reinterpret_cast<const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, op.n_h) +
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, op.n_h) +
                deposit(tile_m, op.a_m + tm, op.n_m - tm);
-  const V* B = reinterpret_cast<const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, op.n_h) +
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, op.n_h) +
                deposit(tile_n, op.b_n + tn, op.n_n - tn);
-  V* C = reinterpret_cast<V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, op.n_h) +
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, op.n_h) +
          deposit(tile_m, op.c_m + tm, op.n_m - tm) + deposit(tile_n, op.c_n + tn, op.n_n - tn);
   TileMap ma, mb;
   make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
@@ -595,9 +625,9 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
     const uint64_t kb = deposit(s, op.b_k + tk, op.n_k - tk);
     __syncthreads();
     for (int i = 0; i < LA; i++)
-      if (a_dst[i] >= 0) (&As[0][0])[(a_dst[i] >> RM) * BM + (a_dst[i] & (BM - 1))] = conjv(A[ka + a_off[i]], op.conj_a);
+      if (a_dst[i] >= 0) (&As[0][0])[(a_dst[i] >> RM) * BM + (a_dst[i] & (BM - 1))] = conjv(ld(A + ka + a_off[i]), op.conj_a);
     for (int i = 0; i < LB; i++)
-      if (b_dst[i] >= 0) (&Bs[0][0])[(b_dst[i] >> RN) * BN + (b_dst[i] & (BN - 1))] = conjv(B[kb + b_off[i]], op.conj_b);
+      if (b_dst[i] >= 0) (&Bs[0][0])[(b_dst[i] >> RN) * BN + (b_dst[i] & (BN - 1))] = conjv(ld(B + kb + b_off[i]), op.conj_b);
     __syncthreads();
     for (int k = 0; k < BK; k++) {
       V a[4], b[4];
@@ -615,9 +645,9 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
     for (int j = 0; j < 4; j++) {
       const int col = tx + 16 * j;
       if (col >= nvalid) continue;
-      V* d = C + ro + deposit(col, op.c_n, tn);
-      if (op.accumulate) { V o = *d; o.x += acc[i][j].x; o.y += acc[i][j].y; *d = o; }
-      else *d = acc[i][j];
+      GMEM V* d = C + ro + deposit(col, op.c_n, tn);
+      if (op.accumulate) { V o = ld(d); o.x += acc[i][j].x; o.y += acc[i][j].y; st(d, o); }
+      else st(d, acc[i][j]);
     }
   }
 }

@@ -1,0 +1,103 @@
+"""The five benchmark workloads (seeded, synthetic) and their cached trees.
+
+  cfg1  3x3 grid circuit, 8 cycles, amplitude <b|C|0^9>; plain greedy tree
+        (alpha = 0.5, tau = 0), no slicing, complex128
+  cfg2  random 3-regular graph, 120 vertices, rank-3 iid complex Gaussian
+        tensors; best of 16 Boltzmann-greedy trees, sliced to width 20
+  cfg3  7x7 grid circuit, 14 cycles, one amplitude; sliced to width 27
+  cfg4  6x6 grid circuit, 12 cycles, one amplitude; gradient of |amp|^2 with
+        respect to every fSim leaf; width at most 28 (sliced only if needed)
+  cfg5  6x9 grid circuit, 12 cycles, six open qubits (central 2x3 block, 64
+        correlated amplitudes); sliced to width 30; a seeded subset of 256
+        slice ids (all ids when there are at most 256)
+
+They stand in for the paper's GRCS / Sycamore circuit files and random-graph
+instances, which are not available here: same gate families, sizes and
+structure, seeded.  Trees come from the Hyper-Greedy sampler (Sec. 3.4) with
+slicing inside the search loop (Sec. 4.7.1); `python -m tn_inputs.configs`
+rewrites the cached trees under tn_inputs/trees/.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from .circuits import circuit_network
+from .graphs import rrg_network
+from .greedy import find_tree
+from .network import Tree
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TREES = os.path.join(HERE, "trees")
+
+CFG5_OPEN = (2 * 9 + 3, 2 * 9 + 4, 2 * 9 + 5, 3 * 9 + 3, 3 * 9 + 4, 3 * 9 + 5)
+
+SPECS = {
+    "cfg1": dict(kind="circuit", R=3, C=3, m=8, open=(), trials=1, slice_width=None),
+    "cfg2": dict(kind="rrg", n=120, trials=16, slice_width=20),
+    "cfg3": dict(kind="circuit", R=7, C=7, m=14, open=(), trials=24, slice_width=27),
+    "cfg4": dict(kind="circuit", R=6, C=6, m=12, open=(), trials=24, slice_width=28),
+    "cfg5": dict(kind="circuit", R=6, C=9, m=12, open=CFG5_OPEN, trials=24, slice_width=30),
+}
+
+
+def network(name: str, seed: int = 0, bitstring: int | None = None):
+    s = SPECS[name]
+    if s["kind"] == "rrg":
+        return rrg_network(s["n"], 3, seed=seed)
+    N = s["R"] * s["C"]
+    if bitstring is None:
+        bitstring = int(np.random.default_rng(seed).integers(0, 2 ** N, dtype=np.uint64)) if N < 64 else 0
+    return circuit_network(s["R"], s["C"], s["m"], seed, bitstring, open_qubits=s["open"])
+
+
+def _path(name, seed):
+    return os.path.join(TREES, f"{name}_seed{seed}.json")
+
+
+def search_tree(name: str, seed: int = 0):
+    s = SPECS[name]
+    net = network(name, seed)
+    return find_tree(net, seed=seed, trials=s["trials"], slice_width=s["slice_width"])
+
+
+def load(name: str, seed: int = 0, bitstring: int | None = None):
+    """(network, tree, sliced indices) of a workload; the tree is read from the
+    cache when present (it depends only on the structure, not on b)."""
+    net = network(name, seed, bitstring)
+    path = _path(name, seed)
+    if os.path.exists(path):
+        d = json.load(open(path))
+        tree = Tree(np.array(d["left"], np.int32), np.array(d["right"], np.int32), meta=d["meta"])
+        return net, tree, list(d["sliced"])
+    tree = search_tree(name, seed)
+    return net, tree, list(tree.meta.get("sliced", []))
+
+
+def slice_subset(d_sliced: int, seed: int = 0, size: int = 256):
+    """Seeded subset of slice ids, ascending (all ids if d_sliced <= size)."""
+    if d_sliced <= size:
+        return list(range(d_sliced))
+    ids = np.random.default_rng(seed).choice(d_sliced, size=size, replace=False)
+    return sorted(int(x) for x in ids)
+
+
+def write_all(seeds=(0,)):
+    os.makedirs(TREES, exist_ok=True)
+    for name in SPECS:
+        for seed in (seeds if name != "cfg2" else range(10)):
+            tree = search_tree(name, seed)
+            meta = {k: (float(v) if isinstance(v, (float, np.floating)) else v)
+                    for k, v in tree.meta.items() if k != "sliced"}
+            d = dict(left=[int(x) for x in tree.left], right=[int(x) for x in tree.right],
+                     sliced=[int(x) for x in tree.meta.get("sliced", [])], meta=meta)
+            json.dump(d, open(_path(name, seed), "w"))
+            print(name, seed, {k: meta[k] for k in ("W", "log2_C") if k in meta},
+                  "sliced", len(d["sliced"]), flush=True)
+
+
+if __name__ == "__main__":
+    write_all()

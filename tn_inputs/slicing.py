@@ -71,3 +71,34 @@ def choose_slices(net: Network, tree: Tree, target_width: int, seed: int = 0,
         if best is None or rec["log2_Cs"] < best["log2_Cs"]:
             best = rec
     return best
+
+
+def extend_slices(net: Network, tree: Tree, sliced, log2_cost_target: float):
+    """Add indices to `sliced` (greedily, the one whose removal lowers the
+    per-slice cost most) until one slice of the tree costs at most
+    2**log2_cost_target.  The result slices the same tree further: every
+    slice of it is a sub-slice of a slice of the original set."""
+    kept, union = tree_masks(net, tree)
+    n = net.n_leaves
+    out_mask = 0
+    for e in net.out_idx:
+        out_mask |= 1 << e
+    S = 0
+    for e in sliced:
+        S |= 1 << e
+    order = list(sliced)
+    internal = list(range(n, 2 * n - 1))
+    while True:
+        per = [2 ** (union[v] & ~S).bit_count() for v in internal]
+        C = sum(per)
+        if C <= 2.0 ** log2_cost_target:
+            return order
+        E = {}
+        for v, c in zip(internal, per):
+            for e in _bits(union[v] & ~S & ~out_mask):
+                E[e] = E.get(e, 0) + c
+        if not E:
+            return order
+        best = max(sorted(E), key=lambda e: E[e])
+        S |= 1 << best
+        order.append(best)
