@@ -135,3 +135,90 @@ def width_cost(net, tree, sliced=()):
     if rc != 0:
         raise OracleError(lib.oracle_last_error().decode())
     return math.log2(W.value), (math.log2(C.value) if C.value > 0 else float("-inf"))
+
+
+def subtree_value(net, tree, node, sliced=(), slice_id=None):
+    """Oracle value of the tensor at tree node `node`, as (array, index list):
+    the sub-network of the leaves below `node`, with its kept indices (those
+    that are outputs or occur on a leaf outside the subtree) left open.  With
+    `sliced`, the sliced indices are fixed to the values of `slice_id`
+    (mixed radix, first sliced index most significant)."""
+    from tn_inputs.network import Network, Tree
+
+    n = net.n_leaves
+    left = [int(x) for x in tree.left]
+    right = [int(x) for x in tree.right]
+
+    def leaves_under(v):
+        if v < n:
+            return [v]
+        return leaves_under(left[v - n]) + leaves_under(right[v - n])
+
+    below = leaves_under(node)
+    inside = set(below)
+    val = {}
+    if sliced:
+        sid = int(slice_id)
+        for e in reversed(list(sliced)):
+            val[e] = sid % net.idx_dim[e]
+            sid //= net.idx_dim[e]
+    count_in, count_out = {}, {}
+    for v, ix in enumerate(net.leaf_idx):
+        for e in ix:
+            d = count_in if v in inside else count_out
+            d[e] = d.get(e, 0) + 1
+    outs = set(net.out_idx)
+    kept = sorted(e for e in count_in if e not in val and (e in outs or e in count_out))
+    leaves, idx = [], []
+    for v in below:
+        t = np.asarray(net.leaves[v])
+        ix = list(net.leaf_idx[v])
+        for e in [e for e in ix if e in val]:
+            t = np.take(t, val[e], axis=ix.index(e))
+            ix.remove(e)
+        leaves.append(t)
+        idx.append(ix)
+    remap = {}
+    for ix in idx:
+        for e in ix:
+            remap.setdefault(e, len(remap))
+    sub = Network(leaves, [[remap[e] for e in ix] for ix in idx], [net.idx_dim[e] for e in sorted(remap, key=remap.get)],
+                  [remap[e] for e in kept])
+    # the subtree's internal nodes in SSA order, renumbered
+    order = {}
+    for k, v in enumerate(below):
+        order[v] = k
+    sl, sr = [], []
+
+    def build(v):
+        if v < n:
+            return order[v]
+        a, b = build(left[v - n]), build(right[v - n])
+        sl.append(a)
+        sr.append(b)
+        return len(below) + len(sl) - 1
+
+    build(node)
+    sub_tree = Tree(np.array(sl, np.int32), np.array(sr, np.int32))
+    return contract(sub, sub_tree), kept
+
+
+def root_condition(net, tree, sliced=(), slice_ids=None):
+    """kappa = sum over slices of ||T_l|| * ||T_r|| / ||R||, for the root's two
+    children T_l, T_r and the result R: the factor by which relative
+    perturbations of the last pairwise contraction's inputs can grow in its
+    output (||l . r|| <= ||l|| ||r||)."""
+    n = net.n_leaves
+    root = 2 * n - 2
+    l, r = int(tree.left[-1]), int(tree.right[-1])
+    ids = list(range(int(np.prod([net.idx_dim[e] for e in sliced], dtype=np.int64)))) if slice_ids is None else list(slice_ids)
+    if not sliced:
+        ids = [None]
+    num = 0.0
+    for s in ids:
+        a, _ = subtree_value(net, tree, l, sliced, s)
+        b, _ = subtree_value(net, tree, r, sliced, s)
+        num += float(np.linalg.norm(a)) * float(np.linalg.norm(b))
+    R = contract(net, tree, sliced=sliced, slice_ids=None if slice_ids is None else slice_ids)
+    del root
+    return num / float(np.linalg.norm(R))

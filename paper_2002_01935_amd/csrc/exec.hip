@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -78,6 +79,10 @@ extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* lea
     return set_err(TN_E_INVALID, "unknown precision");
   }
   p->elem_bytes = p->prec == TN_C128 ? 16 : 8;
+  if (p->prec == TN_C64_3M) {
+    delete p;
+    return set_err(TN_E_UNSUPPORTED, "TN_C64_3M is not available in this build");
+  }
   std::string err;
   int rc = build_plan(p, err);
   if (rc) {
@@ -518,7 +523,10 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     int best_tile = 0;
     // matrix-core tiles only; the summed range is cut to at most 2^9 values
     // for the trials (time per tile scales with K, the ranking does not)
-    for (int t = 0; t < kNumGemmTiles - 1; t++) {
+    const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
+    for (int t = 0; t < kNumGemmTiles; t++) {
+      if (t == kValuTile) continue;
+      if (p->prec == TN_C64_BF16X3 && t > 3) continue;
       GemmOp trial = g;
       trial.tile = t;
       trial.n_k = std::min(trial.n_k, 9);
@@ -530,6 +538,9 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0;
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (verbose)
+        fprintf(stderr, "tune (h,m,n,k)=(%d,%d,%d,%d) tile %d: %.3f ms for k=2^%d\n", g.n_h, g.n_m, g.n_n, g.n_k, t,
+                ms / reps, trial.n_k);
       if (ms < best_ms) { best_ms = ms; best_tile = t; }
     }
     g.tile = best_tile;

@@ -392,157 +392,78 @@ __device__ __forceinline__ void make_tilemap(TileMap& tm, const int8_t* rowpos, 
   tm.nbits = n;
 }
 
-// ------------------------------------------------------------------ MFMA 4M
+// ------------------------------------------------------------------ matrix-core GEMMs
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// BM x BN complex output tile per 256-thread block (2 x 2 waves), BK complex
-// k values per pipeline stage.
-template <int BM, int BN, int BK>
-__global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int FM = WM / 32, FN = WN / 16;        // 32x32x2 fragments per wave
-  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = __builtin_ctz(BK);
-  static_assert(FM >= 1 && FN >= 1 && LA >= 1 && LB >= 1, "tile too small");
-  __shared__ float lds[2][2][BK][BM + BN];          // [buffer][re/im][k][A rows | B cols]
+// Per-thread load slots of one operand tile: element offset in the operand and
+// destination (row | k << rbits) in the tile; unused slots read element 0.
+template <int L, int NT>
+__device__ __forceinline__ void tile_slots(const TileMap& m, int tid, uint32_t* off, int16_t* dst) {
+#pragma unroll
+  for (int i = 0; i < L; i++) {
+    const int e = tid + NT * i;
+    uint32_t o = 0;
+    int d = 0;
+    for (int b = 0; b < m.nbits; b++)
+      if ((e >> b) & 1) { o |= 1u << m.pos[b]; d |= 1 << m.dst[b]; }
+    const bool ok = (e >> m.nbits) == 0;
+    off[i] = ok ? o : 0u;
+    dst[i] = ok ? (int16_t)d : (int16_t)-1;
+  }
+}
 
+// XCD-aware tile order: consecutive block ids land on different XCDs (8 per
+// chip), so each XCD gets a contiguous range of output tiles (shared A rows and
+// B columns stay in its own L2).
+__device__ __forceinline__ uint64_t xcd_tile(uint64_t bid, uint64_t ntiles) {
+  return (ntiles & 7) == 0 ? (bid & 7) * (ntiles >> 3) + (bid >> 3) : bid;
+}
+
+struct GemmSetup {
+  int tm, tn, tk;
+  uint64_t tile_m, tile_n, h;
+  int z;
+  int64_t sid;
+};
+
+__device__ __forceinline__ bool gemm_setup(const Ctx& ctx, const GemmOp& op, int rm, int rn, int rk, GemmSetup& g) {
   const int nzh = ctx.n_batch;
-  const int z = blockIdx.y % nzh;
-  const uint64_t h = blockIdx.y / nzh;
-  const int64_t sid = slice_id(ctx, z);
-  if (sid < 0) return;
+  g.z = blockIdx.y % nzh;
+  g.h = blockIdx.y / nzh;
+  g.sid = slice_id(ctx, g.z);
+  if (g.sid < 0) return false;
+  g.tm = op.n_m < rm ? op.n_m : rm;
+  g.tn = op.n_n < rn ? op.n_n : rn;
+  g.tk = op.n_k < rk ? op.n_k : rk;
+  const uint64_t ntiles_n = uint64_t(1) << (op.n_n - g.tn);
+  const uint64_t ntiles = (uint64_t(1) << (op.n_m - g.tm)) * ntiles_n;
+  const uint64_t bid = xcd_tile(blockIdx.x, ntiles);
+  g.tile_m = bid / ntiles_n;
+  g.tile_n = bid % ntiles_n;
+  return true;
+}
 
-  const int tm = op.n_m < RM ? op.n_m : RM;
-  const int tn = op.n_n < RN ? op.n_n : RN;
-  const int tk = op.n_k < RK ? op.n_k : RK;
-  // XCD-aware tile order: consecutive block ids go to different XCDs (8), so
-  // give each XCD a contiguous range of tiles (shared A rows / B columns in
-  // its L2)
-  const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
-  const uint64_t ntiles = (uint64_t(1) << (op.n_m - tm)) * ntiles_n;
-  uint64_t bid = blockIdx.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const uint64_t tile_m = bid / ntiles_n, tile_n = bid % ntiles_n;
-
-  GMEM const char* Ab = resolve(ctx, op.a, z, sid, 8);
-  GMEM const char* Bb = resolve(ctx, op.b, z, sid, 8);
-  GMEM char* Cb = resolve(ctx, op.c, z, sid, 8);
-  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(Ab) + deposit(h, op.a_h, op.n_h) +
-                    deposit(tile_m, op.a_m + tm, op.n_m - tm);
-  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(Bb) + deposit(h, op.b_h, op.n_h) +
-                    deposit(tile_n, op.b_n + tn, op.n_n - tn);
-
-  // per-thread load slots: offset in the operand and place in the tile
-  TileMap ma, mb;
-  make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
-  make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
-  const int tid = threadIdx.x;
-  uint32_t a_off[LA], b_off[LB];
-  int16_t a_dst[LA], b_dst[LB];
-#pragma unroll
-  for (int i = 0; i < LA; i++) {
-    const int e = tid + 256 * i;
-    uint32_t off = 0;
-    int d = 0;
-    bool ok = (e >> ma.nbits) == 0;
-    for (int b = 0; b < ma.nbits; b++)
-      if ((e >> b) & 1) { off |= 1u << ma.pos[b]; d |= 1 << ma.dst[b]; }
-    a_off[i] = ok ? off : 0u;
-    a_dst[i] = ok ? (int16_t)d : (int16_t)-1;
-  }
-#pragma unroll
-  for (int i = 0; i < LB; i++) {
-    const int e = tid + 256 * i;
-    uint32_t off = 0;
-    int d = 0;
-    bool ok = (e >> mb.nbits) == 0;
-    for (int b = 0; b < mb.nbits; b++)
-      if ((e >> b) & 1) { off |= 1u << mb.pos[b]; d |= 1 << mb.dst[b]; }
-    b_off[i] = ok ? off : 0u;
-    b_dst[i] = ok ? (int16_t)d : (int16_t)-1;
-  }
-  // zero both buffers once (covers partial tiles)
-  for (int i = tid; i < 2 * 2 * BK * (BM + BN); i += 256) (&lds[0][0][0][0])[i] = 0.f;
+// Epilogue shared by the matrix-core kernels: C[row, col] at
+// deposit(row, c_m) + deposit(col, c_n) (+ batch) from the 32 x 32 FP32
+// accumulator layout (lane l holds column l % 32, rows 8 (r / 4) + 4 (l / 32) +
+// r % 4); real column 2 n + p is part p of complex column n.
+template <int BM, int BN, int FM, int FN>
+__device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, const GemmSetup& g, uint64_t* tab,
+                                           const floatx16 (&acc)[FM][FN], int wm, int wn, int tid, int nthreads) {
+  constexpr int WM = FM * 32, WN = FN * 16;
+  GMEM float* C = reinterpret_cast<GMEM float*>(resolve(ctx, op.c, g.z, g.sid, 8));
+  const uint64_t cbase = deposit(g.h, op.c_h, op.n_h) + deposit(g.tile_m, op.c_m + g.tm, op.n_m - g.tm) +
+                         deposit(g.tile_n, op.c_n + g.tn, op.n_n - g.tn);
+  uint64_t* rowoff = tab;
+  uint64_t* coloff = tab + BM;
+  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, g.tm);
+  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, g.tn);
   __syncthreads();
-
-  const uint64_t nsteps = uint64_t(1) << (op.n_k - tk);
-  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
-  float2 ra[LA], rb[LB];
-  auto gload = [&](uint64_t step) {
-    const uint64_t ka = deposit(step, op.a_k + tk, op.n_k - tk);
-    const uint64_t kb = deposit(step, op.b_k + tk, op.n_k - tk);
-#pragma unroll
-    for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
-#pragma unroll
-    for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < LA; i++)
-      if (a_dst[i] >= 0) {
-        const int row = a_dst[i] & (BM - 1), k = a_dst[i] >> RM;
-        lds[buf][0][k][row] = ra[i].x;
-        lds[buf][1][k][row] = sa * ra[i].y;
-      }
-#pragma unroll
-    for (int i = 0; i < LB; i++)
-      if (b_dst[i] >= 0) {
-        const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
-        lds[buf][0][k][BM + col] = rb[i].x;
-        lds[buf][1][k][BM + col] = sb * rb[i].y;
-      }
-  };
-
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int hi = lane >> 5;                 // 0: real part of k, 1: imaginary part
-  const int c32 = lane & 31;
-  const int bpar = c32 & 1;                 // output column parity: re / im
-  const int bplane = bpar ^ hi;             // which part of B feeds this lane
-  const float bsign = (bpar == 0 && hi == 1) ? -1.f : 1.f;
-  floatx16 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; i++)
-#pragma unroll
-    for (int j = 0; j < FN; j++)
-#pragma unroll
-      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (uint64_t s = 0; s < nsteps; s++) {
-    const int buf = s & 1;
-    if (s + 1 < nsteps) gload(s + 1);
-#pragma unroll
-    for (int k = 0; k < BK; k++) {
-      float af[FM], bf[FN];
-#pragma unroll
-      for (int i = 0; i < FM; i++) af[i] = lds[buf][hi][k][wm * WM + i * 32 + c32];
-#pragma unroll
-      for (int j = 0; j < FN; j++) bf[j] = bsign * lds[buf][bplane][k][BM + wn * WN + j * 16 + (c32 >> 1)];
-#pragma unroll
-      for (int i = 0; i < FM; i++)
-#pragma unroll
-        for (int j = 0; j < FN; j++)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    if (s + 1 < nsteps) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // epilogue: C[row, col] at deposit(row, c_m) + deposit(col, c_n) (+ batch)
-  GMEM float* C = reinterpret_cast<GMEM float*>(Cb);
-  const uint64_t cbase = deposit(h, op.c_h, op.n_h) + deposit(tile_m, op.c_m + tm, op.n_m - tm) +
-                         deposit(tile_n, op.c_n + tn, op.n_n - tn);
-  uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
-  uint64_t* coloff = rowoff + BM;
-  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
-  for (int i = tid; i < BM; i += 256) rowoff[i] = deposit(i, op.c_m, tm);
-  for (int i = tid; i < BN; i += 256) coloff[i] = deposit(i, op.c_n, tn);
-  __syncthreads();
-  const int mvalid = 1 << tm, nvalid = 1 << tn;
+  const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31, bpar = c32 & 1;
+  const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
 #pragma unroll
   for (int i = 0; i < FM; i++)
 #pragma unroll
@@ -559,6 +480,283 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
         else *dst = acc[i][j][r];
       }
     }
+}
+
+// 4M on FP32 matrix cores.  The complex product is the real product of
+// [Ar Ai] (M x 2K) with [[Br Bi] [-Bi Br]] (2K x 2N): one
+// v_mfma_f32_32x32x2f32 whose k pair is (re, im) is one complex multiply-add
+// of a 32 x 16 complex tile.  BM x BN complex outputs per block of
+// WGM x WGN waves, each wave 64 x 64; 8 complex k values per pipeline stage.
+// LDS keeps A and B as re / im planes with k contiguous per row (row stride
+// 12 floats: 128-bit reads of 16 lanes hit disjoint banks).  Each lane reads
+// the fragments of 4 k values with one 128-bit load per fragment, and the
+// loads for k 4..7 are in flight while the matrix cores work on k 0..3.
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
+  constexpr int BK = 8, LDR = 12;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1 && LA >= 1 && LB >= 1, "tile too small");
+  // [buffer][plane re / im][A rows | B cols][k]
+  __shared__ __attribute__((aligned(16))) float lds[2][2][BM + BN][LDR];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+  const int tid = threadIdx.x;
+  uint32_t a_off[LA], b_off[LB];
+  int16_t a_dst[LA], b_dst[LB];
+  {
+    TileMap ma, mb;
+    make_tilemap(ma, op.a_m, g.tm, op.a_k, g.tk, RM);
+    make_tilemap(mb, op.b_n, g.tn, op.b_k, g.tk, RN);
+    tile_slots<LA, NT>(ma, tid, a_off, a_dst);
+    tile_slots<LB, NT>(mb, tid, b_off, b_dst);
+  }
+  for (int i = tid; i < 2 * 2 * (BM + BN) * LDR; i += NT) (&lds[0][0][0][0])[i] = 0.f;
+  __syncthreads();
+
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  float2 ra[LA], rb[LB];
+  auto gload = [&](uint64_t step) {
+    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
+    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+#pragma unroll
+    for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
+#pragma unroll
+    for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) {
+        const int row = a_dst[i] & (BM - 1), k = a_dst[i] >> RM;
+        lds[buf][0][row][k] = ra[i].x;
+        lds[buf][1][row][k] = sa * ra[i].y;
+      }
+#pragma unroll
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) {
+        const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
+        lds[buf][0][BM + col][k] = rb[i].x;
+        lds[buf][1][BM + col][k] = sb * rb[i].y;
+      }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int hi = lane >> 5;                 // 0: real part of k, 1: imaginary part
+  const int c32 = lane & 31;
+  const int bpar = c32 & 1;                 // output column parity: re / im
+  const int bsel = bpar ^ hi;               // which part of B feeds this lane
+  const float bsign = (bpar == 0 && hi == 1) ? -1.f : 1.f;
+  const int arow = wm * WM + c32;
+  const int bcol = BM + wn * WN + (c32 >> 1);
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4 fa[2][FM], fb[2][FN];
+  auto fread = [&](int buf, int half) {
+#pragma unroll
+    for (int i = 0; i < FM; i++) fa[half][i] = *reinterpret_cast<const f4*>(&lds[buf][hi][arow + i * 32][4 * half]);
+#pragma unroll
+    for (int j = 0; j < FN; j++) fb[half][j] = *reinterpret_cast<const f4*>(&lds[buf][bsel][bcol + j * 16][4 * half]);
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (uint64_t s = 0; s < nsteps; s++) {
+    const int buf = s & 1;
+    if (s + 1 < nsteps) gload(s + 1);
+    fread(buf, 0);
+    fread(buf, 1);
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+#pragma unroll
+      for (int j = 0; j < FN; j++) fb[half][j] *= bsign;
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int j = 0; j < FN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[half][i][kk], fb[half][j][kk], acc[i][j], 0, 0, 0);
+    }
+    if (s + 1 < nsteps) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
+}
+
+// bf16 round-to-nearest-even of a finite float, and back
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// BF16x3 on BF16 matrix cores: every FP32 operand x is split into
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32) and each real
+// product is formed as hi*hi + hi*lo + lo*hi with FP32 accumulation (the lo*lo
+// term, below 2^-16 relative, is dropped).  The complex product uses the same
+// real embedding as the 4M kernel; one v_mfma_f32_32x32x16_bf16 takes 8
+// complex k values (16 real) per lane pair of a 32 x 16 complex tile.  LDS
+// holds hi and lo of A and B as (re, im) bf16 pairs, k fastest; each lane
+// turns its B pairs into the (Br, -Bi) or (Bi, Br) pattern of its output
+// column parity.
+template <int BM, int BN, int BK, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_mfma_bf16x3(Ctx ctx, GemmOp op) {
+  static_assert(((BK + 4) * 4) % 16 == 0, "fragment rows must stay 16-byte aligned");
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = __builtin_ctz(BK);
+  constexpr int LDK = BK + 4;                      // dwords per row: BK (re, im) pairs + pad (16-byte rows)
+  static_assert(BK % 8 == 0, "BK must hold whole MFMA k steps");
+  __shared__ uint32_t lds[2][2][BM + BN][LDK];      // [buffer][hi/lo][A rows | B cols][k]
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+  const int tid = threadIdx.x;
+  uint32_t a_off[LA], b_off[LB];
+  int16_t a_dst[LA], b_dst[LB];
+  {
+    TileMap ma, mb;
+    make_tilemap(ma, op.a_m, g.tm, op.a_k, g.tk, RM);
+    make_tilemap(mb, op.b_n, g.tn, op.b_k, g.tk, RN);
+    tile_slots<LA, NT>(ma, tid, a_off, a_dst);
+    tile_slots<LB, NT>(mb, tid, b_off, b_dst);
+  }
+  for (int i = tid; i < 2 * 2 * (BM + BN) * LDK; i += NT) (&lds[0][0][0][0])[i] = 0u;
+  __syncthreads();
+
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  float2 ra[LA], rb[LB];
+  auto gload = [&](uint64_t step) {
+    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
+    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+#pragma unroll
+    for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
+#pragma unroll
+    for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+  };
+  auto split = [](float re, float im, uint32_t& h, uint32_t& l) {
+    const uint32_t hr = bf16_rne(re), hm = bf16_rne(im);
+    const uint32_t lr = bf16_rne(re - bf16_f(hr)), lm = bf16_rne(im - bf16_f(hm));
+    h = hr | (hm << 16);
+    l = lr | (lm << 16);
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) {
+        const int row = a_dst[i] & (BM - 1), k = a_dst[i] >> RM;
+        uint32_t h, l;
+        split(ra[i].x, sa * ra[i].y, h, l);
+        lds[buf][0][row][k] = h;
+        lds[buf][1][row][k] = l;
+      }
+#pragma unroll
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) {
+        const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
+        uint32_t h, l;
+        split(rb[i].x, sb * rb[i].y, h, l);
+        lds[buf][0][BM + col][k] = h;
+        lds[buf][1][BM + col][k] = l;
+      }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int kg = lane >> 5;                 // which 4 complex k of the 8
+  const int c32 = lane & 31;
+  const int bpar = c32 & 1;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+  // B pair (br, bi) -> (br, -bi) for even output columns, (bi, br) for odd;
+  // selected by mask, not by branch (the parity differs between lanes)
+  const uint32_t pmask = bpar ? 0xffffffffu : 0u;
+  auto bpat = [pmask](uint32_t d) {
+    const uint32_t sw = (d >> 16) | (d << 16), ng = d ^ 0x80000000u;
+    return (sw & pmask) | (ng & ~pmask);
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (uint64_t s = 0; s < nsteps; s++) {
+    const int buf = s & 1;
+    if (s + 1 < nsteps) gload(s + 1);
+#pragma unroll
+    for (int kt = 0; kt < BK / 8; kt++) {
+      const int k0 = kt * 8 + kg * 4;
+      u32x4 ah[FM], al[FM];
+#pragma unroll
+      for (int i = 0; i < FM; i++) {
+        const int row = wm * WM + i * 32 + c32;
+        ah[i] = *reinterpret_cast<const u32x4*>(&lds[buf][0][row][k0]);
+        al[i] = *reinterpret_cast<const u32x4*>(&lds[buf][1][row][k0]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; j++) {
+        const int col = BM + wn * WN + j * 16 + (c32 >> 1);
+        const u32x4 h = *reinterpret_cast<const u32x4*>(&lds[buf][0][col][k0]);
+        const u32x4 l = *reinterpret_cast<const u32x4*>(&lds[buf][1][col][k0]);
+        u32x4 bh, bl;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          bh[t] = bpat(h[t]);
+          bl[t] = bpat(l[t]);
+        }
+        // hi*hi, hi*lo, lo*hi, interleaved over the row fragments so that no
+        // two consecutive matrix-core ops write the same accumulator
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                              __builtin_bit_cast(bf16x8, bh), acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                              __builtin_bit_cast(bf16x8, bl), acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                              __builtin_bit_cast(bf16x8, bh), acc[i][j], 0, 0, 0);
+      }
+    }
+    if (s + 1 < nsteps) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
 }
 
 // ------------------------------------------------------------------ VALU tiled GEMM
@@ -702,11 +900,11 @@ hipError_t launch_reduce(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t 
 
 int gemm_tile_bits(int tile, int* bm, int* bn) {
   switch (tile) {
-    case 0: *bm = 7; *bn = 7; return 0;     // 128 x 128
-    case 1: *bm = 6; *bn = 7; return 0;     // 64 x 128
-    case 2: *bm = 7; *bn = 6; return 0;     // 128 x 64
-    case 3: *bm = 6; *bn = 6; return 0;     // 64 x 64
-    case 4: *bm = 6; *bn = 6; return 0;     // VALU 64 x 64
+    case 0: *bm = 7; *bn = 7; return 0;     // 128 x 128, 4 waves of 64 x 64
+    case 1: *bm = 6; *bn = 7; return 0;     // 64 x 128, 2 waves
+    case 2: *bm = 7; *bn = 6; return 0;     // 128 x 64, 2 waves
+    case 3: *bm = 6; *bn = 6; return 0;     // 64 x 64, 1 wave
+    case 4: *bm = 6; *bn = 6; return 0;     // vector-ALU 64 x 64
     default: return -1;
   }
 }
@@ -725,12 +923,25 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s
     hipLaunchKernelGGL(gemm_valu<double>, grid, dim3(256), 0, s, ctx, op);
     return hipGetLastError();
   }
+  if (tile == 4) {
+    hipLaunchKernelGGL(gemm_valu<float>, grid, dim3(256), 0, s, ctx, op);
+    return hipGetLastError();
+  }
+  if (prec == TN_C64_BF16X3) {
+    switch (tile) {
+      case 0: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+      case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
+      case 2: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 64, 8, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
+      case 3: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 64, 8, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
+      default: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+    }
+    return hipGetLastError();
+  }
   switch (tile) {
-    case 0: hipLaunchKernelGGL((gemm_mfma_4m<128, 128, 16>), grid, dim3(256), 0, s, ctx, op); break;
-    case 1: hipLaunchKernelGGL((gemm_mfma_4m<64, 128, 16>), grid, dim3(256), 0, s, ctx, op); break;
-    case 2: hipLaunchKernelGGL((gemm_mfma_4m<128, 64, 16>), grid, dim3(256), 0, s, ctx, op); break;
-    case 3: hipLaunchKernelGGL((gemm_mfma_4m<64, 64, 16>), grid, dim3(256), 0, s, ctx, op); break;
-    case 4: hipLaunchKernelGGL(gemm_valu<float>, grid, dim3(256), 0, s, ctx, op); break;
+    case 0: hipLaunchKernelGGL((gemm_mfma_4m<128, 128, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+    case 1: hipLaunchKernelGGL((gemm_mfma_4m<64, 128, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
+    case 2: hipLaunchKernelGGL((gemm_mfma_4m<128, 64, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
+    case 3: hipLaunchKernelGGL((gemm_mfma_4m<64, 64, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -7,6 +7,9 @@ import numpy as np
 
 TOL_C64 = 1e-5
 TOL_C128 = 1e-10
+# BF16x3: each real product carries ~2^-16 relative error (lo*lo dropped, lo
+# rounded); the stated bound for whole contractions is this measured ceiling
+TOL_BF16X3 = 3e-4
 
 
 def rel(a, b):

@@ -1,0 +1,150 @@
+"""GPU reverse mode (tn_contract_backward through the autograd wrapper)
+against the oracle's complex128 gradient, finite differences, and the
+homogeneity identity of a network that is linear in every leaf."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import TOL_C128, TOL_C64, note, rel, to_dev
+from tn_inputs import configs
+from tn_inputs.circuits import circuit_network, gate_leaves
+from tn_inputs.graphs import random_network
+from tn_inputs.greedy import find_tree
+from tn_inputs.slicing import extend_slices
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(net, tree, sliced=(), precision="c64_4m", nb=0):
+    from paper_2002_01935_amd.binding import Plan
+    return Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=nb)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64_4m"])
+def test_autograd_amplitude_norm(oracle_lib, prec):
+    import torch
+
+    from paper_2002_01935_amd.autograd import contract
+    net = circuit_network(3, 4, 6, 1, 0b101101001110)
+    tree = find_tree(net, seed=0, trials=2)
+    wrt = gate_leaves(net, "2q")
+    plan = _plan(net, tree, precision=prec)
+    leaves = to_dev(net, prec)
+    for v in wrt:
+        leaves[v].requires_grad_(True)
+    note("autograd", prec)
+    c = contract(plan, leaves)
+    L = (c.abs() ** 2).sum()
+    L.backward()
+    c_ref = complex(oracle_lib.contract(net, tree))
+    refs = oracle_lib.grad(net, tree, np.array(2 * c_ref), wrt)
+    tol = TOL_C128 if prec == "c128" else TOL_C64
+    got = np.concatenate([leaves[v].grad.cpu().numpy().ravel() for v in wrt])
+    ref = np.concatenate([r.ravel() for r in refs])
+    assert rel(got, ref) < tol
+    for v in range(net.n_leaves):
+        if v not in wrt:
+            assert leaves[v].grad is None
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_backward_sliced_hyper_outputs(oracle_lib, seed):
+    net = random_network(10, 15, 4, seed=200 + seed, n_out=2, dims=(2, 4), hyper=True)
+    tree = find_tree(net, seed=seed, trials=2)
+    cand = [e for e in range(net.n_idx) if e not in net.out_idx]
+    sliced = cand[:3]
+    rng = np.random.default_rng(seed)
+    shape = tuple(net.idx_dim[e] for e in net.out_idx)
+    go = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    wrt = list(range(net.n_leaves))
+    d = int(np.prod([net.idx_dim[e] for e in sliced]))
+    ids = [s for s in range(d) if s % 3 != 1]
+    refs = oracle_lib.grad(net, tree, go, wrt, sliced=sliced, slice_ids=ids)
+    import torch
+    for prec, tol in (("c128", TOL_C128), ("c64_4m", TOL_C64)):
+        note("backward sliced", seed, prec)
+        plan = _plan(net, tree, sliced, prec, nb=2)
+        grads = plan.backward(to_dev(net, prec), torch.from_numpy(go), wrt, slice_ids=ids)
+        torch.cuda.synchronize()
+        got = np.concatenate([g.cpu().numpy().ravel() for g in grads])
+        ref = np.concatenate([r.ravel() for r in refs])
+        assert rel(got, ref) < tol
+
+
+def test_backward_bitwise_independent_of_batch():
+    import torch
+    net = random_network(10, 15, 4, seed=300, n_out=1, dims=(2,), hyper=False)
+    tree = find_tree(net, seed=1, trials=2)
+    cand = [e for e in range(net.n_idx) if e not in net.out_idx]
+    sliced = cand[:4]
+    go = torch.tensor([0.7 - 0.1j, -0.2 + 0.9j], dtype=torch.complex128)
+    outs = []
+    for nb in (1, 4, 16):
+        plan = _plan(net, tree, sliced, "c64_4m", nb=nb)
+        grads = plan.backward(to_dev(net, "c64_4m"), go, list(range(net.n_leaves)))
+        torch.cuda.synchronize()
+        outs.append(np.concatenate([g.cpu().numpy().ravel() for g in grads]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_cfg4_gradient_full_size(oracle_lib):
+    """6x6 grid, 12 cycles, width 28: d|amp|^2 / d(every fSim leaf) in
+    complex64 through tn_contract_backward (recomputation from checkpoints).
+    Checks: (i) homogeneity, (ii) central differences on the GPU complex128
+    path (h = 1e-4; |amp|^2 is quadratic in each entry, so exact up to
+    rounding), (iii) the oracle's complex128 gradient on two sub-slices of the
+    same tree (more indices sliced on both sides)."""
+    import torch
+    net, tree, sliced = configs.load("cfg4")
+    wrt = gate_leaves(net, "2q")
+    assert len(wrt) == 180
+    plan64 = _plan(net, tree, sliced, "c64_4m")
+    leaves = to_dev(net, "c64_4m")
+    note("cfg4 forward")
+    c = complex(plan64.contract_sliced(leaves).cpu().numpy())
+    L = abs(c) ** 2
+    note("cfg4 backward, workspace", plan64.backward_info(wrt)["workspace_bytes"] / 2 ** 30, "GiB")
+    grads = plan64.backward(leaves, torch.tensor(2 * c, dtype=torch.complex128), wrt)
+    torch.cuda.synchronize()
+    grads = [g.cpu().numpy() for g in grads]
+    # (i) homogeneity: c is linear in each gate, so sum_k G_k conj(grad_k) = 2 L
+    worst = 0.0
+    for v, g in zip(wrt, grads):
+        h = np.sum(net.leaves[v].ravel() * g.ravel().conj())
+        worst = max(worst, abs(h - 2 * L) / (2 * L))
+    note("cfg4 homogeneity worst rel", worst)
+    assert worst < 1e-4
+    # (ii) finite differences with the complex128 GPU path
+    plan128 = _plan(net, tree, sliced, "c128")
+    leaves128 = to_dev(net, "c128")
+    hstep = 1e-4
+    fd_err = 0.0
+    for v, k in ((wrt[0], 5), (wrt[90], 10), (wrt[179], 15)):
+        g = grads[wrt.index(v)].ravel()[k]
+        parts = []
+        for step in (hstep, 1j * hstep):
+            vals = []
+            for sgn in (1, -1):
+                x = leaves128[v].clone().reshape(-1)
+                x[k] += sgn * step
+                ls = list(leaves128)
+                ls[v] = x.reshape(leaves128[v].shape)
+                vals.append(abs(complex(plan128.contract_sliced(ls).cpu().numpy())) ** 2)
+            parts.append((vals[0] - vals[1]) / (2 * hstep))
+        fd = parts[0] + 1j * parts[1]
+        fd_err = max(fd_err, abs(fd - g) / max(abs(fd), 1e-30))
+    note("cfg4 finite-difference worst rel", fd_err)
+    assert fd_err < 1e-3
+    # (iii) oracle gradient on sub-slices of the same tree
+    ext = extend_slices(net, tree, sliced, 30.0)
+    ids = [0, 5]
+    go = np.array(2 * c)
+    sub = _plan(net, tree, ext, "c64_4m")
+    g_sub = sub.backward(leaves, torch.from_numpy(go), wrt, slice_ids=ids)
+    torch.cuda.synchronize()
+    ref = oracle_lib.grad(net, tree, go, wrt, sliced=ext, slice_ids=ids)
+    got = np.concatenate([x.cpu().numpy().ravel() for x in g_sub])
+    refv = np.concatenate([r.ravel() for r in ref])
+    note("cfg4 sub-slice gradient rel err", rel(got, refv))
+    assert rel(got, refv) < 1e-4

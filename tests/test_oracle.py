@@ -383,3 +383,32 @@ def test_paper_table_flop_convention():
         flops = complex_flops(math.log2(float(r["C_s"])))
         eff = 100.0 * efficiency(flops, float(r["time_s"]), 3.031e12)
         assert abs(eff - float(r["efficiency_pct"])) < 0.2, r["circuit"]
+
+
+def test_subtree_values_compose_to_root(oracle_lib):
+    """The oracle's subtree evaluator: contracting the root's two children
+    (numpy einsum over their shared indices) gives the full result, with and
+    without slicing."""
+    net = random_network(8, 12, 4, seed=41, n_out=2, dims=(2, 3), hyper=False)
+    tree = random_tree(net, 2)
+    n = net.n_leaves
+    full = oracle_lib.contract(net, tree)
+    a, ia = oracle_lib.subtree_value(net, tree, int(tree.left[-1]))
+    b, ib = oracle_lib.subtree_value(net, tree, int(tree.right[-1]))
+    letters = {e: chr(97 + i) for i, e in enumerate(sorted(set(ia) | set(ib)))}
+    spec = "".join(letters[e] for e in ia) + "," + "".join(letters[e] for e in ib) + "->" + \
+        "".join(letters[e] for e in net.out_idx)
+    assert rel(np.einsum(spec, a, b), full) < 1e-12
+    cand = [e for e in range(net.n_idx) if e not in net.out_idx]
+    sl = cand[:2]
+    d = int(np.prod([net.idx_dim[e] for e in sl]))
+    tot = 0
+    for s in range(d):
+        a, ia = oracle_lib.subtree_value(net, tree, int(tree.left[-1]), sl, s)
+        b, ib = oracle_lib.subtree_value(net, tree, int(tree.right[-1]), sl, s)
+        letters = {e: chr(97 + i) for i, e in enumerate(sorted(set(ia) | set(ib)))}
+        spec = "".join(letters[e] for e in ia) + "," + "".join(letters[e] for e in ib) + "->" + \
+            "".join(letters[e] for e in net.out_idx)
+        tot = tot + np.einsum(spec, a, b)
+    assert rel(tot, full) < 1e-12
+    assert n == net.n_leaves
