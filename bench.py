@@ -35,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK = {"c64_4m": 157.3, "c64_3m": 157.3, "c64_bf16x3": 2500.0, "c128": 78.6}
+KERNEL = {"c64_4m": "gemm_mfma_4m", "c64_3m": "gemm_mfma_3m", "c64_bf16x3": "gemm_mfma_bf16x3", "c128": "gemm_valu"}
 WORKLOADS = {
     "cfg5": "6x9 grid circuit (54 qubits), 12 cycles, fSim(pi/2,pi/6) + sqrtX/Y/W, 6 open qubits "
             "(64 amplitudes), sliced to W_s=30, seeded slice ids",
@@ -168,7 +169,54 @@ def plain_fp64(net, tree, sliced, slice_id, torch):
     return R.cpu().numpy(), time.perf_counter() - t0
 
 
+def summarize_rocprof(path):
+    """Summary of rocprofv3 output under `path`: per (kernel, grid) group the
+    dispatch count and mean / total duration from the kernel trace, and the
+    per-dispatch mean of every PMC counter found (FETCH_SIZE, WRITE_SIZE in
+    KiB).  Prints text for profiles/."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def rows(pattern):
+        for f in sorted(glob.glob(os.path.join(path, "**", pattern), recursive=True)):
+            with open(f) as fh:
+                yield from csv.DictReader(fh)
+
+    def key(r):
+        name = r.get("Kernel_Name", "?")
+        short = name.split("(")[0].replace("void ", "")
+        grid = tuple(r.get(k, "") for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Workgroup_Size_X"))
+        return short[:90], grid
+
+    trace = defaultdict(list)
+    for r in rows("*kernel_trace.csv"):
+        trace[key(r)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    pmc = defaultdict(lambda: defaultdict(list))
+    for r in rows("*counter_collection.csv"):
+        pmc[key(r)][r.get("Counter_Name", "?")].append(float(r.get("Counter_Value", "nan")))
+    out = []
+    if trace:
+        total = sum(sum(v) for v in trace.values())
+        out.append(f"kernel trace: {sum(len(v) for v in trace.values())} dispatches, {total:.1f} ms total")
+        out.append(f"{'kernel':60s} {'grid(x,y,z,wg)':28s} {'calls':>6s} {'mean ms':>10s} {'total ms':>10s} {'share':>6s}")
+        for (k, g), v in sorted(trace.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            out.append(f"{k[:60]:60s} {str(g):28s} {len(v):6d} {sum(v) / len(v):10.3f} {sum(v):10.1f} {sum(v) / total:6.1%}")
+    if pmc:
+        out.append("PMC counters (mean per dispatch):")
+        agg = []
+        for (k, g), cs in pmc.items():
+            agg.append(((k, g), {c: sum(v) / len(v) for c, v in cs.items()}, max(len(v) for v in cs.values())))
+        for (k, g), cs, n in sorted(agg, key=lambda a: -sum(a[1].values()))[:25]:
+            vals = "  ".join(f"{c}={v:.4g}" for c, v in sorted(cs.items()))
+            out.append(f"{k[:60]:60s} {str(g):28s} n={n:4d}  {vals}")
+    print("\n".join(out))
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
+        summarize_rocprof(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -176,6 +224,8 @@ def main():
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="c64_4m", choices=sorted(PEAK))
     ap.add_argument("--slices-per-step", type=int, default=2)
+    ap.add_argument("--inflight", type=int, default=1, help="slices contracted together per graph replay")
+    ap.add_argument("--no-variants", action="store_true", help="skip timing the other precisions")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -195,7 +245,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     net, tree, sliced = configs.load(args.workload)
-    plan = Plan(net, tree, sliced=sliced, precision=args.precision, max_inflight_slices=1)
+    plan = Plan(net, tree, sliced=sliced, precision=args.precision, max_inflight_slices=args.inflight)
     info = plan.info()
     ids_all = configs.slice_subset(info["d_sliced"], seed=0, size=256)
     B = max(1, min(args.slices_per_step, len(ids_all)))
@@ -250,7 +300,7 @@ def main():
         peak = PEAK[args.precision]
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "gemm_mfma_4m" if args.precision == "c64_4m" else args.precision,
+                "kernel": KERNEL[args.precision],
                 "node": dom["node"], "flops_per_launch": dom["flops"], "avg_launch_ms": round(avg_s * 1e3, 3),
                 "time_share": round(dom["ms"] / total_ms, 4),
                 "time_by_kernel_class": {k: round(v / total_ms, 4) for k, v in sorted(by_kind.items())}}
@@ -273,18 +323,45 @@ def main():
         log(f"cpu oracle: {cpu['value'] * 1e3:.3f} GFLOP/s on {threads} threads ({tc:.1f} s)")
 
     plain = None
+    plain_ref = None
     if not args.no_plain:
         try:
             ref, tp = plain_fp64(net, tree, sliced, ids_all[0], torch)
             plan1 = plan.contract_sliced(leaves, slice_ids=[ids_all[0]], out=out, workspace=ws).cpu().numpy()
             err = float(np.linalg.norm(plan1 - ref) / np.linalg.norm(ref))
             plain = {"s_per_slice": round(tp, 4), "speedup": round(tp / per_slice, 2),
-                     "rel_err_c64_vs_fp64_plain": err}
+                     "rel_err_vs_fp64_plain": err}
             log(f"plain fp64 path: {tp:.2f} s/slice, speedup {tp / per_slice:.1f}x, rel err {err:.2e}")
-            del ref
+            plain_ref = ref
         except torch.cuda.OutOfMemoryError as e:   # the plain path materialises every permute
             plain = {"error": f"out of memory: {e}"[:200]}
         torch.cuda.empty_cache()
+
+    variants = None
+    if not args.no_variants and args.precision == "c64_4m":
+        variants = {}
+        del ws
+        torch.cuda.empty_cache()
+        for prec in ("c64_3m", "c64_bf16x3"):
+            vp = Plan(net, tree, sliced=sliced, precision=prec, max_inflight_slices=args.inflight)
+            vws = vp.workspace()
+            vp.tune(vws)
+            vp.contract_sliced(leaves, slice_ids=step_ids(0), out=out, workspace=vws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(args.steps):
+                vp.contract_sliced(leaves, slice_ids=step_ids(args.warmup + s), out=out, workspace=vws)
+            torch.cuda.synchronize()
+            ve = time.perf_counter() - t0
+            rec = {"value": round(info["flops_per_slice"] * n_slices / ve / 1e12, 3), "unit": "TFLOP/s",
+                   "s_per_slice": round(ve / n_slices, 4)}
+            if plain_ref is not None:
+                v1 = vp.contract_sliced(leaves, slice_ids=[ids_all[0]], out=out, workspace=vws).cpu().numpy()
+                rec["rel_err_vs_fp64_plain"] = float(np.linalg.norm(v1 - plain_ref) / np.linalg.norm(plain_ref))
+            variants[prec] = rec
+            log(f"variant {prec}: {rec}")
+            del vws, vp
+            torch.cuda.empty_cache()
 
     res = {
         "metric": "TFLOP/s on contraction tree + s/amplitude at stated error vs FP64, vs plain path",
@@ -297,7 +374,7 @@ def main():
                    "flops_8C_per_slice": info["flops_per_slice"], "amplitudes": n_amps},
         "s_per_slice": round(per_slice, 4),
         "s_per_amplitude_extrapolated": round(per_slice * info["d_sliced"] / n_amps, 4),
-        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain,
+        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain, "variants": variants,
     }
     print(json.dumps(res), flush=True)
 

@@ -79,10 +79,6 @@ extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* lea
     return set_err(TN_E_INVALID, "unknown precision");
   }
   p->elem_bytes = p->prec == TN_C128 ? 16 : 8;
-  if (p->prec == TN_C64_3M) {
-    delete p;
-    return set_err(TN_E_UNSUPPORTED, "TN_C64_3M is not available in this build");
-  }
   std::string err;
   int rc = build_plan(p, err);
   if (rc) {

@@ -440,6 +440,7 @@ __device__ __forceinline__ bool gemm_setup(const Ctx& ctx, const GemmOp& op, int
   g.tk = op.n_k < rk ? op.n_k : rk;
   const uint64_t ntiles_n = uint64_t(1) << (op.n_n - g.tn);
   const uint64_t ntiles = (uint64_t(1) << (op.n_m - g.tm)) * ntiles_n;
+  if (blockIdx.x >= ntiles) return false;
   const uint64_t bid = xcd_tile(blockIdx.x, ntiles);
   g.tile_m = bid / ntiles_n;
   g.tile_n = bid % ntiles_n;
@@ -601,6 +602,157 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
   }
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
+}
+
+// 3M (Gauss) on FP32 matrix cores: with T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2 and Im = T3 - T1 - T2: three real
+// products per complex product instead of four.  Each v_mfma_f32_32x32x2f32
+// takes two complex k values of one real plane for a 32 x 32 complex tile.
+// LDS keeps the planes A: re, im, re + im and B: re, im, re + im, k
+// contiguous per row, with the k order (k & 1) * 4 + (k >> 1) inside each
+// 8-value stage so that the four k values a lane feeds (its half of the k
+// pairs) are one 128-bit read.  BM x BN complex outputs per block of
+// WGM x WGN waves, each wave 64 x 32.
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_mfma_3m(Ctx ctx, GemmOp op) {
+  constexpr int BK = 8, LDR = 12;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1 && LA >= 1 && LB >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) float lds[2][3][BM + BN][LDR];   // [buffer][re, im, re+im][rows | cols][k]
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+  const int tid = threadIdx.x;
+  uint32_t a_off[LA], b_off[LB];
+  int16_t a_dst[LA], b_dst[LB];
+  {
+    TileMap ma, mb;
+    make_tilemap(ma, op.a_m, g.tm, op.a_k, g.tk, RM);
+    make_tilemap(mb, op.b_n, g.tn, op.b_k, g.tk, RN);
+    tile_slots<LA, NT>(ma, tid, a_off, a_dst);
+    tile_slots<LB, NT>(mb, tid, b_off, b_dst);
+  }
+  for (int i = tid; i < 2 * 3 * (BM + BN) * LDR; i += NT) (&lds[0][0][0][0])[i] = 0.f;
+  __syncthreads();
+
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  float2 ra[LA], rb[LB];
+  auto gload = [&](uint64_t step) {
+    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
+    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+#pragma unroll
+    for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
+#pragma unroll
+    for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+  };
+  auto kpos = [](int k) { return (k & 1) * 4 + (k >> 1); };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; i++)
+      if (a_dst[i] >= 0) {
+        const int row = a_dst[i] & (BM - 1), k = kpos(a_dst[i] >> RM);
+        const float re = ra[i].x, im = sa * ra[i].y;
+        lds[buf][0][row][k] = re;
+        lds[buf][1][row][k] = im;
+        lds[buf][2][row][k] = re + im;
+      }
+#pragma unroll
+    for (int i = 0; i < LB; i++)
+      if (b_dst[i] >= 0) {
+        const int col = b_dst[i] & (BN - 1), k = kpos(b_dst[i] >> RN);
+        const float re = rb[i].x, im = sb * rb[i].y;
+        lds[buf][0][BM + col][k] = re;
+        lds[buf][1][BM + col][k] = im;
+        lds[buf][2][BM + col][k] = re + im;
+      }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int hi = lane >> 5, c32 = lane & 31;
+  const int arow = wm * WM + c32, bcol = BM + wn * WN + c32;
+  floatx16 acc[3][FM][FN];
+#pragma unroll
+  for (int t = 0; t < 3; t++)
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int j = 0; j < FN; j++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[t][i][j][r] = 0.f;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (uint64_t s = 0; s < nsteps; s++) {
+    const int buf = s & 1;
+    if (s + 1 < nsteps) gload(s + 1);
+    f4 fa[3][FM], fb[3][FN];
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+#pragma unroll
+      for (int i = 0; i < FM; i++) fa[t][i] = *reinterpret_cast<const f4*>(&lds[buf][t][arow + i * 32][4 * hi]);
+#pragma unroll
+      for (int j = 0; j < FN; j++) fb[t][j] = *reinterpret_cast<const f4*>(&lds[buf][t][bcol + j * 32][4 * hi]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+      for (int t = 0; t < 3; t++)
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int j = 0; j < FN; j++)
+            acc[t][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[t][i][kk], fb[t][j][kk], acc[t][i][j], 0, 0, 0);
+    if (s + 1 < nsteps) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: lane holds complex column c32 of each 32 x 32 tile
+  GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
+  const uint64_t cbase = deposit(g.h, op.c_h, op.n_h) + deposit(g.tile_m, op.c_m + g.tm, op.n_m - g.tm) +
+                         deposit(g.tile_n, op.c_n + g.tn, op.n_n - g.tn);
+  uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
+  uint64_t* coloff = rowoff + BM;
+  for (int i = tid; i < BM; i += NT) rowoff[i] = deposit(i, op.c_m, g.tm);
+  for (int i = tid; i < BN; i += NT) coloff[i] = deposit(i, op.c_n, g.tn);
+  __syncthreads();
+  const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      const int col = wn * WN + j * 32 + c32;
+      if (col >= nvalid) continue;
+      const uint64_t co = coloff[col];
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+        if (row >= mvalid) continue;
+        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+        float2 v;
+        v.x = t1 - t2;
+        v.y = t3 - t1 - t2;
+        GMEM float2* dst = C + cbase + rowoff[row] + co;
+        if (op.accumulate) {
+          const float2 o = ld(dst);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        st(dst, v);
+      }
+    }
 }
 
 // bf16 round-to-nearest-even of a finite float, and back
@@ -925,6 +1077,17 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s
   }
   if (tile == 4) {
     hipLaunchKernelGGL(gemm_valu<float>, grid, dim3(256), 0, s, ctx, op);
+    return hipGetLastError();
+  }
+  if (prec == TN_C64_3M) {
+    switch (tile) {
+      // block tiles as in gemm_tile_bits; waves of 64 x 32
+      case 0: hipLaunchKernelGGL((gemm_mfma_3m<128, 128, 2, 4>), grid, dim3(512), 0, s, ctx, op); break;
+      case 1: hipLaunchKernelGGL((gemm_mfma_3m<64, 128, 1, 4>), grid, dim3(256), 0, s, ctx, op); break;
+      case 2: hipLaunchKernelGGL((gemm_mfma_3m<128, 64, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+      case 3: hipLaunchKernelGGL((gemm_mfma_3m<64, 64, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   if (prec == TN_C64_BF16X3) {

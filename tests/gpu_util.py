@@ -10,6 +10,8 @@ TOL_C128 = 1e-10
 # BF16x3: each real product carries ~2^-16 relative error (lo*lo dropped, lo
 # rounded); the stated bound for whole contractions is this measured ceiling
 TOL_BF16X3 = 3e-4
+# 3M: Im = T3 - T1 - T2 loses componentwise accuracy when |Im| << |Re|
+TOL_3M = 1e-4
 
 
 def rel(a, b):
@@ -46,3 +48,28 @@ def gpu_contract(net, tree, precision="c64_4m"):
     out = p.contract(to_dev(net, precision))
     torch.cuda.synchronize()
     return out.cpu().numpy()
+
+
+def project(net, extra, values):
+    """Network whose contraction equals one sub-slice: for each extra index e
+    with value x, the entries of the first leaf holding e with x_e != x are
+    set to zero (multiplying the network by a delta on e)."""
+    leaves = [np.array(t, copy=True) for t in net.leaves]
+    for e, x in zip(extra, values):
+        v = next(v for v, ix in enumerate(net.leaf_idx) if e in ix)
+        ax = net.leaf_idx[v].index(e)
+        sel = [slice(None)] * leaves[v].ndim
+        for y in range(net.idx_dim[e]):
+            if y != x:
+                sel[ax] = y
+                leaves[v][tuple(sel)] = 0
+    return net.with_leaves(leaves)
+
+
+def sub_slice_id(slice_id, extra_values, extra_dims):
+    """Slice id in the extended sliced set (original list, then the extra
+    indices): mixed radix with the first index most significant."""
+    sid = int(slice_id)
+    for x, d in zip(extra_values, extra_dims):
+        sid = sid * int(d) + int(x)
+    return sid

@@ -1,0 +1,61 @@
+"""Full-size parity in the launch configuration bench.py times (one in-flight
+slice, autotuned tiles, graph replay): a whole slice of cfg5 (width 30) and
+of cfg3 (width 27) runs on the GPU with a few more indices projected out of
+the leaves (tests/gpu_util.project), and the oracle evaluates the matching
+sub-slice of the same tree.  Tolerance: complex64 relative error 1e-5, or a
+normwise backward error of the last contraction within 1e-5 when the result
+is cancellation-heavy; BF16x3 within its stated bound."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import TOL_BF16X3, TOL_C64, note, project, rel, sub_slice_id, to_dev
+from tn_inputs import configs
+from tn_inputs.slicing import extend_slices
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(name, prec, log2_target, slice_pos, seed_vals, oracle_lib):
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    net, tree, sliced = configs.load(name)
+    ids = configs.slice_subset(2 ** len(sliced), seed=0, size=256)
+    s = ids[slice_pos]
+    ext = extend_slices(net, tree, sliced, log2_target)
+    extra = ext[len(sliced):]
+    vals = [int(x) for x in np.random.default_rng(seed_vals).integers(0, 2, size=len(extra))]
+    pnet = project(net, extra, vals)
+    plan = Plan(net, tree, sliced=sliced, precision=prec, max_inflight_slices=1)
+    ws = plan.workspace()
+    plan.tune(ws)
+    note(name, prec, "slice", s, "extra", len(extra), "workspace GiB", plan.info()["workspace_bytes"] / 2 ** 30)
+    got = plan.contract_sliced(to_dev(pnet, prec), slice_ids=[s], workspace=ws).cpu().numpy()
+    torch.cuda.synchronize()
+    del ws
+    sid = sub_slice_id(s, vals, [net.idx_dim[e] for e in extra])
+    ref = oracle_lib.contract(net, tree, sliced=ext, slice_ids=[sid])
+    err = rel(got, ref)
+    return err, net, tree, ext, sid
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c64_bf16x3"])
+def test_cfg5_full_slice(oracle_lib, prec):
+    err, net, tree, ext, sid = _run("cfg5", prec, 33.0, 7, 1, oracle_lib)
+    note("cfg5", prec, "rel err", err)
+    if prec == "c64_bf16x3":
+        assert err < TOL_BF16X3
+    elif err > TOL_C64:
+        kappa = oracle_lib.root_condition(net, tree, ext, slice_ids=[sid])
+        note("cfg5 kappa", kappa, "backward", err / kappa)
+        assert err / kappa < TOL_C64
+
+
+def test_cfg3_full_slice(oracle_lib):
+    err, net, tree, ext, sid = _run("cfg3", "c64_4m", 31.0, 3, 2, oracle_lib)
+    note("cfg3 rel err", err)
+    if err > TOL_C64:
+        kappa = oracle_lib.root_condition(net, tree, ext, slice_ids=[sid])
+        note("cfg3 kappa", kappa, "backward", err / kappa)
+        assert err / kappa < TOL_C64

@@ -4,7 +4,7 @@ inputs.  Tolerances: 1e-10 relative for complex128, 1e-5 for complex64."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import TOL_BF16X3, TOL_C128, TOL_C64, gpu_contract, gpu_sliced, note, rel
+from tests.gpu_util import TOL_3M, TOL_BF16X3, TOL_C128, TOL_C64, gpu_contract, gpu_sliced, note, rel
 from tn_inputs.circuits import circuit_network
 from tn_inputs.graphs import pairwise_network, random_network, rrg_network
 from tn_inputs.greedy import find_tree
@@ -22,10 +22,10 @@ SHAPES = [(0, 0, 0, 0), (0, 0, 0, 10), (0, 3, 2, 0), (0, 10, 2, 3), (0, 2, 10, 3
           (2, 6, 6, 3), (0, 12, 5, 1), (0, 8, 7, 11), (1, 9, 3, 6), (0, 5, 8, 2)]
 
 
-TOLS = {"c64_4m": TOL_C64, "c128": TOL_C128, "c64_bf16x3": TOL_BF16X3}
+TOLS = {"c64_4m": TOL_C64, "c128": TOL_C128, "c64_bf16x3": TOL_BF16X3, "c64_3m": TOL_3M}
 
 
-@pytest.mark.parametrize("prec", ["c64_4m", "c128", "c64_bf16x3"])
+@pytest.mark.parametrize("prec", ["c64_4m", "c128", "c64_bf16x3", "c64_3m"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_pairwise(oracle_lib, shape, prec):
     net = pairwise_network(*shape, seed=sum(shape) * 7 + len(prec))
@@ -87,6 +87,10 @@ def test_cfg2_rrg(oracle_lib, seed):
     gbf = complex(gpu_sliced(net, tree, sliced=sl, precision="c64_bf16x3"))
     note("cfg2 bf16x3 rel err", abs(gbf - ref) / abs(ref))
     assert abs(gbf - ref) <= TOL_BF16X3 * abs(ref)
+    g3m = complex(gpu_sliced(net, tree, sliced=sl, precision="c64_3m"))
+    err3 = abs(g3m - ref) / abs(ref)
+    note("cfg2 3m rel err", err3, "backward", err3 / kappa)
+    assert err3 <= TOL_3M or err3 / kappa <= TOL_C64
 
 
 def test_sliced_subsets_and_batches(oracle_lib):
