@@ -213,9 +213,24 @@ def summarize_rocprof(path):
     print("\n".join(out))
 
 
+def copy_calibration():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): run under
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE to scale those counters."""
+    import torch
+    x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": x.numel() * 4, "dispatches": 3}))
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         summarize_rocprof(sys.argv[2])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
+        copy_calibration()
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -522,7 +522,7 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
     for (int t = 0; t < kNumGemmTiles; t++) {
       if (t == kValuTile) continue;
-      if (p->prec == TN_C64_BF16X3 && t > 3) continue;
+      if (p->prec != TN_C64_4M && t >= kNumTilesShared) continue;
       GemmOp trial = g;
       trial.tile = t;
       trial.n_k = std::min(trial.n_k, 9);

@@ -492,7 +492,7 @@ __device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, con
 // 12 floats: 128-bit reads of 16 lanes hit disjoint banks).  Each lane reads
 // the fragments of 4 k values with one 128-bit load per fragment, and the
 // loads for k 4..7 are in flight while the matrix cores work on k 0..3.
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, int PRIO = 0>
 __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_mfma_4m(Ctx ctx, GemmOp op) {
   constexpr int BK = 8, LDR = 12;
   constexpr int NT = 64 * WGM * WGN;
@@ -586,6 +586,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     if (s + 1 < nsteps) gload(s + 1);
     fread(buf, 0);
     fread(buf, 1);
+    if (PRIO) __builtin_amdgcn_s_setprio(1);   // keep this wave's matrix-core issue ahead of the other wave's loads
 #pragma unroll
     for (int half = 0; half < 2; half++) {
 #pragma unroll
@@ -598,6 +599,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
           for (int j = 0; j < FN; j++)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[half][i][kk], fb[half][j][kk], acc[i][j], 0, 0, 0);
     }
+    if (PRIO) __builtin_amdgcn_s_setprio(0);
     if (s + 1 < nsteps) sstore(buf ^ 1);
     __syncthreads();
   }
@@ -1057,6 +1059,8 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 2: *bm = 7; *bn = 6; return 0;     // 128 x 64, 2 waves
     case 3: *bm = 6; *bn = 6; return 0;     // 64 x 64, 1 wave
     case 4: *bm = 6; *bn = 6; return 0;     // vector-ALU 64 x 64
+    case 5: *bm = 8; *bn = 7; return 0;     // 256 x 128, 8 waves (4M only)
+    case 6: *bm = 7; *bn = 7; return 0;     // 128 x 128 with raised matrix-core priority (4M only)
     default: return -1;
   }
 }
@@ -1096,7 +1100,7 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s
       case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
       case 2: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 64, 8, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
       case 3: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 64, 8, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
-      default: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+      default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
@@ -1105,6 +1109,8 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s
     case 1: hipLaunchKernelGGL((gemm_mfma_4m<64, 128, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
     case 2: hipLaunchKernelGGL((gemm_mfma_4m<128, 64, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
     case 3: hipLaunchKernelGGL((gemm_mfma_4m<64, 64, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
+    case 5: hipLaunchKernelGGL((gemm_mfma_4m<256, 128, 4, 2>), grid, dim3(512), 0, s, ctx, op); break;
+    case 6: hipLaunchKernelGGL((gemm_mfma_4m<128, 128, 2, 2, 1>), grid, dim3(256), 0, s, ctx, op); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
