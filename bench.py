@@ -49,6 +49,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "rowops.h", "tn_internal.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2002_01935_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, precision, workload, log2_hmnk):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    record (profiles/traffic_*.json: FETCH_SIZE + WRITE_SIZE, each scaled by
+    a plain copy's reading), or None when no record matches this kernel,
+    node and the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if (rec.get("kernel") != kernel or rec.get("precision") != precision or rec.get("log2_hmnk") != log2_hmnk
+            or rec.get("kernel_sources_sha256") != kernel_sources_sha256()):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def permute_any(x, perm, torch):
     """x.permute(perm).contiguous() for any rank: axes that stay adjacent are
     merged first; if more than 16 groups remain (the limit of the copy kernel
@@ -170,46 +195,78 @@ def plain_fp64(net, tree, sliced, slice_id, torch):
 
 
 def summarize_rocprof(path):
-    """Summary of rocprofv3 output under `path`: per (kernel, grid) group the
-    dispatch count and mean / total duration from the kernel trace, and the
+    """Summary of rocprofv3 output under `path` (rocpd SQLite databases, or CSV
+    files from --output-format csv): per (kernel, grid) group the dispatch
+    count and mean / min / total duration from the kernel trace, and the
     per-dispatch mean of every PMC counter found (FETCH_SIZE, WRITE_SIZE in
     KiB).  Prints text for profiles/."""
     import csv
     import glob
+    import sqlite3
     from collections import defaultdict
 
-    def rows(pattern):
-        for f in sorted(glob.glob(os.path.join(path, "**", pattern), recursive=True)):
-            with open(f) as fh:
-                yield from csv.DictReader(fh)
-
-    def key(r):
-        name = r.get("Kernel_Name", "?")
-        short = name.split("(")[0].replace("void ", "")
-        grid = tuple(r.get(k, "") for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Workgroup_Size_X"))
-        return short[:90], grid
+    def short(name):
+        return name.split("(")[0].replace("void ", "").replace("tn::", "")[:70]
 
     trace = defaultdict(list)
-    for r in rows("*kernel_trace.csv"):
-        trace[key(r)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
     pmc = defaultdict(lambda: defaultdict(list))
-    for r in rows("*counter_collection.csv"):
-        pmc[key(r)][r.get("Counter_Name", "?")].append(float(r.get("Counter_Value", "nan")))
+    longest = []
+    for f in sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True)):
+        con = sqlite3.connect(f)
+        tabs = {r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")}
+        if "kernels" in tabs:
+            for name, gx, gy, gz, wx, dur in con.execute(
+                    "select name, grid_x, grid_y, grid_z, workgroup_x, duration from kernels"):
+                trace[(short(name), (gx, gy, gz, wx))].append(dur / 1e6)
+            # the longest dispatches, with their counters when this is a PMC run
+            for did, name, dur in con.execute(
+                    "select dispatch_id, name, duration from kernels order by duration desc limit 6"):
+                cs = {}
+                if "counters_collection" in tabs:
+                    for cname, val in con.execute(
+                            "select counter_name, value from counters_collection where dispatch_id = ?", (did,)):
+                        cs[cname] = float(val)
+                longest.append((short(name), dur / 1e6, cs))
+        if "counters_collection" in tabs:
+            for name, gx, gy, gz, wx, cname, val in con.execute(
+                    "select kernel_name, grid_size_x, grid_size_y, grid_size_z, workgroup_size_x, counter_name, value "
+                    "from counters_collection"):
+                pmc[(short(name), (gx, gy, gz, wx))][cname].append(float(val))
+        con.close()
+    for f in sorted(glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                g = tuple(int(r[k]) for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Workgroup_Size_X"))
+                trace[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                g = tuple(int(r[k]) for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Workgroup_Size_X"))
+                pmc[(short(r["Kernel_Name"]), g)][r["Counter_Name"]].append(float(r["Counter_Value"]))
     out = []
     if trace:
         total = sum(sum(v) for v in trace.values())
         out.append(f"kernel trace: {sum(len(v) for v in trace.values())} dispatches, {total:.1f} ms total")
-        out.append(f"{'kernel':60s} {'grid(x,y,z,wg)':28s} {'calls':>6s} {'mean ms':>10s} {'total ms':>10s} {'share':>6s}")
-        for (k, g), v in sorted(trace.items(), key=lambda kv: -sum(kv[1]))[:25]:
-            out.append(f"{k[:60]:60s} {str(g):28s} {len(v):6d} {sum(v) / len(v):10.3f} {sum(v):10.1f} {sum(v) / total:6.1%}")
+        out.append(f"{'kernel':52s} {'grid x,y,z / wg':26s} {'calls':>6s} {'mean ms':>10s} {'min ms':>10s} "
+                   f"{'total ms':>10s} {'share':>6s}")
+        for (k, g), v in sorted(trace.items(), key=lambda kv: -sum(kv[1]))[:30]:
+            gs = f"{g[0]},{g[1]},{g[2]}/{g[3]}"
+            out.append(f"{k[:52]:52s} {gs:26s} {len(v):6d} {sum(v) / len(v):10.3f} {min(v):10.3f} "
+                       f"{sum(v):10.1f} {sum(v) / total:6.1%}")
     if pmc:
-        out.append("PMC counters (mean per dispatch):")
+        out.append("PMC counters (mean per dispatch, KiB for FETCH_SIZE / WRITE_SIZE):")
         agg = []
         for (k, g), cs in pmc.items():
             agg.append(((k, g), {c: sum(v) / len(v) for c, v in cs.items()}, max(len(v) for v in cs.values())))
-        for (k, g), cs, n in sorted(agg, key=lambda a: -sum(a[1].values()))[:25]:
-            vals = "  ".join(f"{c}={v:.4g}" for c, v in sorted(cs.items()))
-            out.append(f"{k[:60]:60s} {str(g):28s} n={n:4d}  {vals}")
+        for (k, g), cs, n in sorted(agg, key=lambda a: -sum(a[1].values()))[:30]:
+            vals = "  ".join(f"{c}={v:.6g}" for c, v in sorted(cs.items()))
+            gs = f"{g[0]},{g[1]},{g[2]}/{g[3]}"
+            out.append(f"{k[:52]:52s} {gs:26s} n={n:4d}  {vals}")
+    if longest:
+        out.append("longest dispatches (ms, counters of that dispatch):")
+        for name, ms, cs in sorted(longest, key=lambda x: -x[1]):
+            vals = "  ".join(f"{c}={v:.6g}" for c, v in sorted(cs.items()))
+            out.append(f"{name[:52]:52s} {ms:10.3f}  {vals}")
     print("\n".join(out))
 
 
@@ -225,7 +282,46 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 4, "dispatches": 3}))
 
 
+def node_bench(spec, precision, reps):
+    """One pairwise contraction node, A[M][K] x B[N][K] -> C[M][N] (binary
+    indices, canonical layouts, seeded complex normal entries), timed per
+    launch with HIP events through tn_contract_sliced_timed: the dominant
+    GEMM shape of a workload in isolation, for kernel profiles."""
+    import numpy as np
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    from tn_inputs.network import Network, Tree
+    m, n, k = (int(x) for x in spec.split(","))
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    g = torch.Generator().manual_seed(0)
+    a = torch.randn(2 ** (m + k), dtype=torch.complex64, generator=g).numpy().reshape([2] * (m + k))
+    b = torch.randn(2 ** (n + k), dtype=torch.complex64, generator=g).numpy().reshape([2] * (n + k))
+    net = Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
+    tree = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    plan = Plan(net, tree, precision=precision)
+    ws = plan.workspace()
+    leaves = [torch.from_numpy(np.ascontiguousarray(t)).to("cuda", plan.storage_dtype) for t in net.leaves]
+    out = torch.empty(plan.out_shape, dtype=torch.complex128, device="cuda")
+    plan.tune(ws)
+    plan.contract_sliced_timed(leaves, out=out, workspace=ws)
+    best = None
+    for _ in range(reps):
+        _, ops = plan.contract_sliced_timed(leaves, out=out, workspace=ws)
+        op = max(ops, key=lambda o: o["ms"])
+        best = op if best is None or op["ms"] < best["ms"] else best
+    node = plan.nodes()[0]
+    print(json.dumps({"mode": "node", "shape_mnk": [m, n, k], "precision": precision, "kernel_class": node["kclass"],
+                      "kernel": best["kind"], "ms": round(best["ms"], 4),
+                      "tflops": round(best["flops"] / best["ms"] / 1e9, 2),
+                      "gbs": round(best["bytes"] / best["ms"] / 1e6, 1), "reps": reps}))
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--node":
+        prec = sys.argv[3] if len(sys.argv) > 3 else "c64_4m"
+        node_bench(sys.argv[2], prec, int(sys.argv[4]) if len(sys.argv) > 4 else 3)
+        return
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         summarize_rocprof(sys.argv[2])
         return
@@ -319,6 +415,11 @@ def main():
                 "node": dom["node"], "flops_per_launch": dom["flops"], "avg_launch_ms": round(avg_s * 1e3, 3),
                 "time_share": round(dom["ms"] / total_ms, 4),
                 "time_by_kernel_class": {k: round(v / total_ms, 4) for k, v in sorted(by_kind.items())}}
+        nodes = plan.nodes()
+        if 0 <= dom["node"] - net.n_leaves < len(nodes):
+            nd = nodes[dom["node"] - net.n_leaves]
+            roof["log2_hmnk"] = [nd["logH"], nd["logM"], nd["logN"], nd["logK"]]
+            roof["traffic"] = measured_traffic(KERNEL[args.precision], args.precision, args.workload, roof["log2_hmnk"])
         log(f"dominant gemm node {dom['node']}: {avg_s * 1e3:.2f} ms/launch, {achieved:.1f} TFLOP/s")
 
     cpu = None

@@ -209,6 +209,32 @@ static std::vector<Op> forward_program(const tn_plan_s* p, int mode) {
     nb = (int)outbits.size();
     for (int b : outbits) src_pos.push_back((int8_t)L.pos_of(b));
   }
+  // Unsliced contraction: the root's ops write the output buffer directly
+  // (the root layout is already the output order and the storage type).
+  if (mode == 0 && n > 1) {
+    const int root_node = 2 * n - 2;
+    bool direct = true;
+    for (const Op& o : prog) {
+      if (o.node != root_node) continue;
+      if (o.kind == OpKind::Fill || (o.kind == OpKind::Row && o.row.accumulate) ||
+          (o.kind == OpKind::Gemm && o.gemm.accumulate))
+        direct = false;
+    }
+    if (direct) {
+      auto redirect = [&](Ref& r) {
+        if (r.kind == 1 && r.off == p->root_off) { r.kind = 2; r.slot = p->slot_out; r.off = 0; }
+      };
+      for (Op& o : prog) {
+        if (o.node != root_node) continue;
+        if (o.kind == OpKind::Row || o.kind == OpKind::RowReduce) redirect(o.row.c);
+        else if (o.kind == OpKind::Gemm) redirect(o.gemm.c);
+      }
+      Op c;
+      c.kind = OpKind::Counter;
+      prog.push_back(c);
+      return prog;
+    }
+  }
   Op t;
   std::memset(&t.perm, 0, sizeof t.perm);
   std::memset(&t.accum, 0, sizeof t.accum);

@@ -34,271 +34,10 @@ namespace tn {
 // compiler emit global (not flat) loads and stores, whose completion counters
 // are independent of LDS traffic, so prefetches overlap computation.
 #define GMEM __attribute__((address_space(1)))
+// Constant address space: uniform read-only data, loaded with scalar loads.
+#define CMEM __attribute__((address_space(4)))
 
-// ------------------------------------------------------------------ helpers
-
-template <typename T> struct C2;
-template <> struct C2<float> { using t = float2; };
-template <> struct C2<double> { using t = double2; };
-
-template <typename V> struct Scal;
-template <> struct Scal<float2> { using t = float; };
-template <> struct Scal<double2> { using t = double; };
-
-// element load / store through the native two-lane vector type
-template <typename V>
-__device__ __forceinline__ V ld(GMEM const V* p) {
-  typedef typename Scal<V>::t T;
-  typedef T n2 __attribute__((ext_vector_type(2)));
-  const n2 v = *reinterpret_cast<GMEM const n2*>(p);
-  V r;
-  r.x = v.x;
-  r.y = v.y;
-  return r;
-}
-
-template <typename V>
-__device__ __forceinline__ void st(GMEM V* p, V v) {
-  typedef typename Scal<V>::t T;
-  typedef T n2 __attribute__((ext_vector_type(2)));
-  n2 w;
-  w.x = v.x;
-  w.y = v.y;
-  *reinterpret_cast<GMEM n2*>(p) = w;
-}
-
-template <typename V>
-__device__ __forceinline__ V cmul(V a, V b) {
-  V r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
-
-template <typename V>
-__device__ __forceinline__ V cfma(V acc, V a, V b) {
-  acc.x = acc.x + a.x * b.x - a.y * b.y;
-  acc.y = acc.y + a.x * b.y + a.y * b.x;
-  return acc;
-}
-
-__device__ __forceinline__ uint64_t deposit(uint64_t v, const int8_t* pos, int n) {
-  uint64_t off = 0;
-  for (int i = 0; i < n; i++)
-    if ((v >> i) & 1) off |= uint64_t(1) << pos[i];
-  return off;
-}
-
-// position list may hold -1 (bit absent from this operand)
-__device__ __forceinline__ uint64_t deposit_opt(uint64_t v, const int8_t* pos, int n) {
-  uint64_t off = 0;
-  for (int i = 0; i < n; i++)
-    if (((v >> i) & 1) && pos[i] >= 0) off |= uint64_t(1) << pos[i];
-  return off;
-}
-
-__device__ __forceinline__ int64_t slice_id(const Ctx& ctx, int z) {
-  const int64_t cnt = *reinterpret_cast<const int64_t*>(ctx.ws + ctx.counter_off);
-  const int64_t* sids = reinterpret_cast<const int64_t*>(ctx.ws + ctx.sid_off);
-  return sids[cnt * ctx.n_batch + z];
-}
-
-// Base address of an operand for in-flight slice z with slice id sid.
-__device__ __forceinline__ GMEM char* resolve(const Ctx& ctx, const Ref& r, int z, int64_t sid, int ebytes) {
-  if (r.kind == 1)
-    return reinterpret_cast<GMEM char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
-  const uint64_t p = reinterpret_cast<const uint64_t*>(ctx.ws + ctx.ptrtab_off)[r.slot];
-  uint64_t off = 0;
-  for (int i = 0; i < r.n_slice; i++)
-    if ((sid >> r.slice_bit[i]) & 1) off |= uint64_t(1) << r.slice_pos[i];
-  return reinterpret_cast<GMEM char*>(p) + off * uint64_t(ebytes);
-}
-
-template <typename V>
-__device__ __forceinline__ V conjv(V a, int c) {
-  if (c) a.y = -a.y;
-  return a;
-}
-
-// ------------------------------------------------------------------ row kernel
-
-constexpr int kRowThreads = 256;
-constexpr int kKTabBits = 10;
-
-template <typename T, int NIN>
-__global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
-  using V = typename C2<T>::t;
-  const int z = blockIdx.y;
-  const int64_t sid = slice_id(ctx, z);
-  if (sid < 0) return;
-  __shared__ uint32_t ktab_a[1 << kKTabBits];
-  __shared__ uint32_t ktab_b[1 << kKTabBits];
-  const int klo = op.n_k < kKTabBits ? op.n_k : kKTabBits;
-  for (int k = threadIdx.x; k < (1 << klo); k += blockDim.x) {
-    ktab_a[k] = (uint32_t)deposit(k, op.k_a, klo);
-    ktab_b[k] = (uint32_t)deposit(k, op.k_b, klo);
-  }
-  __syncthreads();
-  const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (row >> op.n_rows) return;
-  const int eb = sizeof(V);
-  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
-  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
-  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-  const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
-  const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
-  const uint64_t oc = deposit(row, op.row_c, op.n_rows);
-  uint64_t inb[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; j++) inb[j] = deposit(j, op.in_b, op.n_in);
-  V acc[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; j++) { acc[j].x = 0; acc[j].y = 0; }
-  const uint64_t nk = uint64_t(1) << op.n_k;
-  const uint64_t lomask = (uint64_t(1) << klo) - 1;
-  uint64_t hia = 0, hib = 0;
-  for (uint64_t k = 0; k < nk; k++) {
-    if ((k & lomask) == 0 && k) {
-      hia = deposit(k >> klo, op.k_a + klo, op.n_k - klo);
-      hib = deposit(k >> klo, op.k_b + klo, op.n_k - klo);
-    }
-    const V a = conjv(ld(A + oa + hia + ktab_a[k & lomask]), op.conj_a);
-    const uint64_t bb = ob + hib + ktab_b[k & lomask];
-#pragma unroll
-    for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a, conjv(ld(B + bb + inb[j]), op.conj_b));
-  }
-#pragma unroll
-  for (int j = 0; j < NIN; j++) {
-    const uint64_t c = oc + deposit(j, op.in_c, op.n_in);
-    if (op.accumulate) {
-      V o = ld(Cp + c);
-      o.x += acc[j].x;
-      o.y += acc[j].y;
-      st(Cp + c, o);
-    } else {
-      st(Cp + c, acc[j]);
-    }
-  }
-}
-
-// ------------------------------------------------------------------ split-K
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  // fixed butterfly order: identical result on every run
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-template <typename T, int NIN>
-__global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) {
-  using V = typename C2<T>::t;
-  const int z = blockIdx.y;
-  const int64_t sid = slice_id(ctx, z);
-  if (sid < 0) return;
-  __shared__ uint32_t ktab_a[1 << kKTabBits];
-  __shared__ uint32_t ktab_b[1 << kKTabBits];
-  const int klo = op.n_k < kKTabBits ? op.n_k : kKTabBits;
-  for (int k = threadIdx.x; k < (1 << klo); k += blockDim.x) {
-    ktab_a[k] = (uint32_t)deposit(k, op.k_a, klo);
-    ktab_b[k] = (uint32_t)deposit(k, op.k_b, klo);
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
-  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
-  const uint64_t row = wave >> ks;
-  const uint64_t chunk = wave & ((uint64_t(1) << ks) - 1);
-  if (row >> op.n_rows) return;
-  const int eb = sizeof(V);
-  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
-  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
-  const uint64_t oa = deposit_opt(row, op.row_a, op.n_rows);
-  const uint64_t ob = deposit_opt(row, op.row_b, op.n_rows);
-  uint64_t inb[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; j++) inb[j] = deposit(j, op.in_b, op.n_in);
-  T ar[NIN], ai[NIN];
-#pragma unroll
-  for (int j = 0; j < NIN; j++) { ar[j] = 0; ai[j] = 0; }
-  const int cbits = op.n_k - ks;                  // >= 6
-  const uint64_t csize = uint64_t(1) << cbits;
-  const uint64_t k0 = chunk << cbits;
-  const uint64_t lomask = (uint64_t(1) << klo) - 1;
-  uint64_t cur_hi = ~uint64_t(0), hia = 0, hib = 0;
-  for (uint64_t kk = lane; kk < csize; kk += 64) {
-    const uint64_t k = k0 + kk;
-    const uint64_t hi = k >> klo;
-    if (hi != cur_hi) {
-      cur_hi = hi;
-      hia = deposit(hi, op.k_a + klo, op.n_k - klo);
-      hib = deposit(hi, op.k_b + klo, op.n_k - klo);
-    }
-    const V a = conjv(ld(A + oa + hia + ktab_a[k & lomask]), op.conj_a);
-    const uint64_t bb = ob + hib + ktab_b[k & lomask];
-#pragma unroll
-    for (int j = 0; j < NIN; j++) {
-      const V b = conjv(ld(B + bb + inb[j]), op.conj_b);
-      ar[j] += a.x * b.x - a.y * b.y;
-      ai[j] += a.x * b.y + a.y * b.x;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NIN; j++) { ar[j] = wave_sum(ar[j]); ai[j] = wave_sum(ai[j]); }
-  if (lane != 0) return;
-  if (ks == 0) {
-    GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-    const uint64_t oc = deposit(row, op.row_c, op.n_rows);
-#pragma unroll
-    for (int j = 0; j < NIN; j++) {
-      const uint64_t c = oc + deposit(j, op.in_c, op.n_in);
-      V o;
-      o.x = ar[j];
-      o.y = ai[j];
-      if (op.accumulate) { V p = ld(Cp + c); o.x += p.x; o.y += p.y; }
-      st(Cp + c, o);
-    }
-  } else {
-    GMEM V* P = reinterpret_cast<GMEM V*>(resolve(ctx, op.part, z, sid, eb));
-    const uint64_t base = ((chunk << op.n_rows) + row) * NIN;
-#pragma unroll
-    for (int j = 0; j < NIN; j++) {
-      V o;
-      o.x = ar[j];
-      o.y = ai[j];
-      st(P + base + j, o);
-    }
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) {
-  using V = typename C2<T>::t;
-  const int z = blockIdx.y;
-  const int64_t sid = slice_id(ctx, z);
-  if (sid < 0) return;
-  const int nin = 1 << op.n_in;
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const uint64_t row = t / nin;
-  const int j = (int)(t % nin);
-  if (row >> op.n_rows) return;
-  const int eb = sizeof(V);
-  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, eb));
-  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-  V s;
-  s.x = 0;
-  s.y = 0;
-  const uint64_t nch = uint64_t(1) << op.k_split_bits;
-  for (uint64_t ch = 0; ch < nch; ch++) {
-    const V p = ld(P + ((ch << op.n_rows) + row) * nin + j);
-    s.x += p.x;
-    s.y += p.y;
-  }
-  const uint64_t c = deposit(row, op.row_c, op.n_rows) + deposit(j, op.in_c, op.n_in);
-  if (op.accumulate) { V p = ld(Cp + c); s.x += p.x; s.y += p.y; }
-  st(Cp + c, s);
-}
+#include "rowops.h"
 
 // ------------------------------------------------------------------ permute / accumulate
 
@@ -308,8 +47,8 @@ __global__ __launch_bounds__(256) void permute_kernel(Ctx ctx, PermuteOp op) {
   using VD = typename C2<TD>::t;
   const uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >> op.n_bits) return;
-  const uint64_t so = deposit(e, op.src_pos, op.n_bits);
-  const uint64_t dof = deposit(e, op.dst_pos, op.n_bits);
+  const uint64_t so = deposit(e, op.src_pos, 0, op.n_bits);
+  const uint64_t dof = deposit(e, op.dst_pos, 0, op.n_bits);
   const int z0 = op.per_slice_serial ? 0 : blockIdx.y;
   const int z1 = op.per_slice_serial ? ctx.n_batch : blockIdx.y + 1;
   for (int z = z0; z < z1; z++) {
@@ -372,24 +111,42 @@ __global__ __launch_bounds__(256) void fill_kernel(uint64_t base, uint64_t n_wor
 // and its (row, k) position in the tile.
 struct TileMap {
   int nbits;
-  int8_t pos[kMaxTileBits];   // position in the operand of enumeration bit i
-  int8_t dst[kMaxTileBits];   // destination bit in the tile index (k * R + row)
+  int8_t pos[kMaxTileBits];   // operand position of tile bit i (rows first, then k)
+  int8_t dst[kMaxTileBits];   // its bit in the tile index (row | k << rlog)
+  int8_t rank[kMaxTileBits];  // its place in increasing position order = bit of the enumeration index
 };
 
+// All loops run over the fixed maximum with predication, so the arrays are
+// indexed statically and stay in registers.
 __device__ __forceinline__ void make_tilemap(TileMap& tm, const int8_t* rowpos, int rbits,
                                              const int8_t* kpos, int kbits, int rlog) {
-  // gather (position, destination) pairs and sort by position (tiny insertion sort)
-  int n = 0;
-  for (int i = 0; i < rbits; i++) { tm.pos[n] = rowpos[i]; tm.dst[n] = (int8_t)i; n++; }
-  for (int i = 0; i < kbits; i++) { tm.pos[n] = kpos[i]; tm.dst[n] = (int8_t)(rlog + i); n++; }
-  for (int i = 1; i < n; i++) {
-    int8_t p = tm.pos[i], d = tm.dst[i];
-    int j = i - 1;
-    while (j >= 0 && tm.pos[j] > p) { tm.pos[j + 1] = tm.pos[j]; tm.dst[j + 1] = tm.dst[j]; j--; }
-    tm.pos[j + 1] = p;
-    tm.dst[j + 1] = d;
+#pragma unroll
+  for (int i = 0; i < kMaxTileBits; i++) {
+    const bool isr = i < rbits, isk = !isr && i < rbits + kbits;
+    tm.pos[i] = (int8_t)(isr ? pos_at(rowpos, i) : (isk ? pos_at(kpos, i - rbits) : 127));
+    tm.dst[i] = (int8_t)(isr ? i : (isk ? rlog + i - rbits : 0));
   }
-  tm.nbits = n;
+#pragma unroll
+  for (int i = 0; i < kMaxTileBits; i++) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxTileBits; j++) r += tm.pos[j] < tm.pos[i];
+    tm.rank[i] = (int8_t)r;
+  }
+  tm.nbits = rbits + kbits;
+}
+
+// Operand offset and tile index of enumeration element e.
+__device__ __forceinline__ void tile_elem(const TileMap& m, uint32_t e, uint64_t& off, int& d) {
+  off = 0;
+  d = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxTileBits; i++)
+    if (i < m.nbits) {
+      const uint32_t bit = (e >> m.rank[i]) & 1u;
+      off |= uint64_t(bit) << m.pos[i];
+      d |= int(bit) << m.dst[i];
+    }
 }
 
 // ------------------------------------------------------------------ matrix-core GEMMs
@@ -405,12 +162,11 @@ __device__ __forceinline__ void tile_slots(const TileMap& m, int tid, uint32_t* 
 #pragma unroll
   for (int i = 0; i < L; i++) {
     const int e = tid + NT * i;
-    uint32_t o = 0;
-    int d = 0;
-    for (int b = 0; b < m.nbits; b++)
-      if ((e >> b) & 1) { o |= 1u << m.pos[b]; d |= 1 << m.dst[b]; }
+    uint64_t o;
+    int d;
+    tile_elem(m, e, o, d);
     const bool ok = (e >> m.nbits) == 0;
-    off[i] = ok ? o : 0u;
+    off[i] = ok ? (uint32_t)o : 0u;
     dst[i] = ok ? (int16_t)d : (int16_t)-1;
   }
 }
@@ -441,9 +197,17 @@ __device__ __forceinline__ bool gemm_setup(const Ctx& ctx, const GemmOp& op, int
   const uint64_t ntiles_n = uint64_t(1) << (op.n_n - g.tn);
   const uint64_t ntiles = (uint64_t(1) << (op.n_m - g.tm)) * ntiles_n;
   if (blockIdx.x >= ntiles) return false;
-  const uint64_t bid = xcd_tile(blockIdx.x, ntiles);
-  g.tile_m = bid / ntiles_n;
-  g.tile_n = bid % ntiles_n;
+  // Within an XCD's range, tiles run in groups of up to 8 tile rows with the
+  // row index fastest: the ~64 tiles resident on one XCD at a time then span
+  // about 8 x 8 tiles, so each A row panel and B column panel they stream is
+  // shared by ~8 of them through that XCD's L2 (instead of one A panel shared
+  // by all and every B panel fetched separately).
+  const uint64_t t = xcd_tile(blockIdx.x, ntiles);
+  const int gm_bits = (op.n_m - g.tm) < 3 ? (op.n_m - g.tm) : 3;
+  const uint64_t in_group = ntiles_n << gm_bits;
+  const uint64_t r = t & (in_group - 1);
+  g.tile_m = ((t >> (op.n_n - g.tn + gm_bits)) << gm_bits) + (r & ((uint64_t(1) << gm_bits) - 1));
+  g.tile_n = r >> gm_bits;
   return true;
 }
 
@@ -456,29 +220,45 @@ __device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, con
                                            const floatx16 (&acc)[FM][FN], int wm, int wn, int tid, int nthreads) {
   constexpr int WM = FM * 32, WN = FN * 16;
   GMEM float* C = reinterpret_cast<GMEM float*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit(g.h, op.c_h, op.n_h) + deposit(g.tile_m, op.c_m + g.tm, op.n_m - g.tm) +
-                         deposit(g.tile_n, op.c_n + g.tn, op.n_n - g.tn);
+  const uint64_t cbase = deposit(g.h, op.c_h, 0, op.n_h) + deposit(g.tile_m, op.c_m, g.tm, op.n_m - g.tm) +
+                         deposit(g.tile_n, op.c_n, g.tn, op.n_n - g.tn);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
-  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, g.tm);
-  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, g.tn);
+  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
+  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, 0, g.tn);
   __syncthreads();
-  const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31, bpar = c32 & 1;
+  const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31, odd = c32 & 1;
   const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
+  GMEM float2* C2 = reinterpret_cast<GMEM float2*>(C);
+  // Lanes 2c and 2c+1 hold the real and imaginary parts of column c for the
+  // same rows.  They swap one value per row pair (r, r+1) so that the even
+  // lane owns the complex value of row r and the odd lane that of row r+1:
+  // one 8-byte store per complex output.
 #pragma unroll
   for (int i = 0; i < FM; i++)
 #pragma unroll
     for (int j = 0; j < FN; j++) {
       const int col = wn * WN + j * 16 + (c32 >> 1);
-      if (col >= nvalid) continue;
-      const uint64_t co = coloff[col];
+      const uint64_t co = col < nvalid ? coloff[col] : 0;
 #pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-        if (row >= mvalid) continue;
-        GMEM float* dst = C + 2 * (cbase + rowoff[row] + co) + bpar;
-        if (op.accumulate) *dst += acc[i][j][r];
-        else *dst = acc[i][j][r];
+      for (int r = 0; r < 16; r += 2) {
+        const float send = odd ? acc[i][j][r] : acc[i][j][r + 1];
+        // quad permutation [1, 0, 3, 2]: exchange with the neighbouring lane
+        const float recv = __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0xB1, 0xF, 0xF, false));
+        float2 v;
+        v.x = odd ? recv : acc[i][j][r];
+        v.y = odd ? acc[i][j][r + 1] : recv;
+        const int rr = r + odd;
+        const int row = wm * WM + i * 32 + 8 * (rr >> 2) + 4 * hi + (rr & 3);
+        if (col >= nvalid || row >= mvalid) continue;
+        GMEM float2* dst = C2 + cbase + rowoff[row] + co;
+        if (op.accumulate) {
+          const float2 o = ld(dst);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        st(dst, v);
       }
     }
 }
@@ -501,16 +281,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
   constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
   static_assert(FM >= 1 && FN >= 1 && LA >= 1 && LB >= 1, "tile too small");
-  // [buffer][plane re / im][A rows | B cols][k]
-  __shared__ __attribute__((aligned(16))) float lds[2][2][BM + BN][LDR];
+  // [buffer][plane re / im][A rows | B cols][k]; the planes are 32 words
+  // apart modulo the 64 LDS banks, so the lanes of a B fragment read, which
+  // mix the two planes, stay conflict-free
+  constexpr int PS = (BM + BN) * LDR + 32;
+  __shared__ __attribute__((aligned(16))) float lds[4 * PS];
   static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+  auto L = [&](int buf, int plane, int row) -> float* { return &lds[(2 * buf + plane) * PS + row * LDR]; };
 
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -521,34 +305,48 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     tile_slots<LA, NT>(ma, tid, a_off, a_dst);
     tile_slots<LB, NT>(mb, tid, b_off, b_dst);
   }
-  for (int i = tid; i < 2 * 2 * (BM + BN) * LDR; i += NT) (&lds[0][0][0][0])[i] = 0.f;
+  for (int i = tid; i < 4 * PS; i += NT) lds[i] = 0.f;
+  // k offsets of consecutive pipeline stages, advanced stage by stage with
+  // the per-carry deltas of each operand (LDS table: no scalar loads, whose
+  // completion wait would also drain the LDS reads in flight, in the loop)
+  __shared__ uint64_t kdel[2][kMaxBits];
+  for (int t = tid; t < op.n_k - g.tk; t += NT) {
+    const uint64_t c = (uint64_t(1) << t) - 1;
+    kdel[0][t] = step_delta(c, op.a_k, g.tk);
+    kdel[1][t] = step_delta(c, op.b_k, g.tk);
+  }
   __syncthreads();
 
   const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
   const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
   float2 ra[LA], rb[LB];
-  auto gload = [&](uint64_t step) {
-    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
-    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+  uint64_t ka = 0, kb = 0, kstep = 0;
+  auto gload = [&]() {
 #pragma unroll
     for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
 #pragma unroll
     for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+    if (kstep + 1 < nsteps) {
+      const int t = __builtin_ctzll(~kstep);
+      ka += kdel[0][t];
+      kb += kdel[1][t];
+    }
+    kstep++;
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < LA; i++)
       if (a_dst[i] >= 0) {
         const int row = a_dst[i] & (BM - 1), k = a_dst[i] >> RM;
-        lds[buf][0][row][k] = ra[i].x;
-        lds[buf][1][row][k] = sa * ra[i].y;
+        L(buf, 0, row)[k] = ra[i].x;
+        L(buf, 1, row)[k] = sa * ra[i].y;
       }
 #pragma unroll
     for (int i = 0; i < LB; i++)
       if (b_dst[i] >= 0) {
         const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
-        lds[buf][0][BM + col][k] = rb[i].x;
-        lds[buf][1][BM + col][k] = sb * rb[i].y;
+        L(buf, 0, BM + col)[k] = rb[i].x;
+        L(buf, 1, BM + col)[k] = sb * rb[i].y;
       }
   };
 
@@ -573,17 +371,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   f4 fa[2][FM], fb[2][FN];
   auto fread = [&](int buf, int half) {
 #pragma unroll
-    for (int i = 0; i < FM; i++) fa[half][i] = *reinterpret_cast<const f4*>(&lds[buf][hi][arow + i * 32][4 * half]);
+    for (int i = 0; i < FM; i++) fa[half][i] = *reinterpret_cast<const f4*>(L(buf, hi, arow + i * 32) + 4 * half);
 #pragma unroll
-    for (int j = 0; j < FN; j++) fb[half][j] = *reinterpret_cast<const f4*>(&lds[buf][bsel][bcol + j * 16][4 * half]);
+    for (int j = 0; j < FN; j++) fb[half][j] = *reinterpret_cast<const f4*>(L(buf, bsel, bcol + j * 16) + 4 * half);
   };
 
-  gload(0);
+  gload();
   sstore(0);
   __syncthreads();
   for (uint64_t s = 0; s < nsteps; s++) {
     const int buf = s & 1;
-    if (s + 1 < nsteps) gload(s + 1);
+    if (s + 1 < nsteps) gload();
     fread(buf, 0);
     fread(buf, 1);
     if (PRIO) __builtin_amdgcn_s_setprio(1);   // keep this wave's matrix-core issue ahead of the other wave's loads
@@ -603,7 +401,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     if (s + 1 < nsteps) sstore(buf ^ 1);
     __syncthreads();
   }
-  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
 // 3M (Gauss) on FP32 matrix cores: with T1 = Ar Br, T2 = Ai Bi and
@@ -630,9 +428,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -644,18 +442,32 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     tile_slots<LB, NT>(mb, tid, b_off, b_dst);
   }
   for (int i = tid; i < 2 * 3 * (BM + BN) * LDR; i += NT) (&lds[0][0][0][0])[i] = 0.f;
+  // k offsets of consecutive pipeline stages, advanced stage by stage with
+  // the per-carry deltas of each operand (LDS table: no scalar loads, whose
+  // completion wait would also drain the LDS reads in flight, in the loop)
+  __shared__ uint64_t kdel[2][kMaxBits];
+  for (int t = tid; t < op.n_k - g.tk; t += NT) {
+    const uint64_t c = (uint64_t(1) << t) - 1;
+    kdel[0][t] = step_delta(c, op.a_k, g.tk);
+    kdel[1][t] = step_delta(c, op.b_k, g.tk);
+  }
   __syncthreads();
 
   const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
   const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
   float2 ra[LA], rb[LB];
-  auto gload = [&](uint64_t step) {
-    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
-    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+  uint64_t ka = 0, kb = 0, kstep = 0;
+  auto gload = [&]() {
 #pragma unroll
     for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
 #pragma unroll
     for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+    if (kstep + 1 < nsteps) {
+      const int t = __builtin_ctzll(~kstep);
+      ka += kdel[0][t];
+      kb += kdel[1][t];
+    }
+    kstep++;
   };
   auto kpos = [](int k) { return (k & 1) * 4 + (k >> 1); };
   auto sstore = [&](int buf) {
@@ -694,12 +506,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
         for (int r = 0; r < 16; r++) acc[t][i][j][r] = 0.f;
   typedef float f4 __attribute__((ext_vector_type(4)));
 
-  gload(0);
+  gload();
   sstore(0);
   __syncthreads();
   for (uint64_t s = 0; s < nsteps; s++) {
     const int buf = s & 1;
-    if (s + 1 < nsteps) gload(s + 1);
+    if (s + 1 < nsteps) gload();
     f4 fa[3][FM], fb[3][FN];
 #pragma unroll
     for (int t = 0; t < 3; t++) {
@@ -723,12 +535,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 
   // epilogue: lane holds complex column c32 of each 32 x 32 tile
   GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit(g.h, op.c_h, op.n_h) + deposit(g.tile_m, op.c_m + g.tm, op.n_m - g.tm) +
-                         deposit(g.tile_n, op.c_n + g.tn, op.n_n - g.tn);
+  const uint64_t cbase = deposit(g.h, op.c_h, 0, op.n_h) + deposit(g.tile_m, op.c_m, g.tm, op.n_m - g.tm) +
+                         deposit(g.tile_n, op.c_n, g.tn, op.n_n - g.tn);
   uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
   uint64_t* coloff = rowoff + BM;
-  for (int i = tid; i < BM; i += NT) rowoff[i] = deposit(i, op.c_m, g.tm);
-  for (int i = tid; i < BN; i += NT) coloff[i] = deposit(i, op.c_n, g.tn);
+  for (int i = tid; i < BM; i += NT) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
+  for (int i = tid; i < BN; i += NT) coloff[i] = deposit(i, op.c_n, 0, g.tn);
   __syncthreads();
   const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
 #pragma unroll
@@ -790,9 +602,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, op.n_h) + deposit(g.tile_m, op.a_m + g.tm, op.n_m - g.tm);
+                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, op.n_h) + deposit(g.tile_n, op.b_n + g.tn, op.n_n - g.tn);
+                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -804,18 +616,32 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     tile_slots<LB, NT>(mb, tid, b_off, b_dst);
   }
   for (int i = tid; i < 2 * 2 * (BM + BN) * LDK; i += NT) (&lds[0][0][0][0])[i] = 0u;
+  // k offsets of consecutive pipeline stages, advanced stage by stage with
+  // the per-carry deltas of each operand (LDS table: no scalar loads, whose
+  // completion wait would also drain the LDS reads in flight, in the loop)
+  __shared__ uint64_t kdel[2][kMaxBits];
+  for (int t = tid; t < op.n_k - g.tk; t += NT) {
+    const uint64_t c = (uint64_t(1) << t) - 1;
+    kdel[0][t] = step_delta(c, op.a_k, g.tk);
+    kdel[1][t] = step_delta(c, op.b_k, g.tk);
+  }
   __syncthreads();
 
   const uint64_t nsteps = uint64_t(1) << (op.n_k - g.tk);
   const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
   float2 ra[LA], rb[LB];
-  auto gload = [&](uint64_t step) {
-    const uint64_t ka = deposit(step, op.a_k + g.tk, op.n_k - g.tk);
-    const uint64_t kb = deposit(step, op.b_k + g.tk, op.n_k - g.tk);
+  uint64_t ka = 0, kb = 0, kstep = 0;
+  auto gload = [&]() {
 #pragma unroll
     for (int i = 0; i < LA; i++) ra[i] = ld(A + ka + a_off[i]);
 #pragma unroll
     for (int i = 0; i < LB; i++) rb[i] = ld(B + kb + b_off[i]);
+    if (kstep + 1 < nsteps) {
+      const int t = __builtin_ctzll(~kstep);
+      ka += kdel[0][t];
+      kb += kdel[1][t];
+    }
+    kstep++;
   };
   auto split = [](float re, float im, uint32_t& h, uint32_t& l) {
     const uint32_t hr = bf16_rne(re), hm = bf16_rne(im);
@@ -864,12 +690,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     return (sw & pmask) | (ng & ~pmask);
   };
 
-  gload(0);
+  gload();
   sstore(0);
   __syncthreads();
   for (uint64_t s = 0; s < nsteps; s++) {
     const int buf = s & 1;
-    if (s + 1 < nsteps) gload(s + 1);
+    if (s + 1 < nsteps) gload();
 #pragma unroll
     for (int kt = 0; kt < BK / 8; kt++) {
       const int k0 = kt * 8 + kg * 4;
@@ -935,12 +761,12 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
   const uint64_t tile_m = blockIdx.x / ntiles_n, tile_n = blockIdx.x % ntiles_n;
   const int eb = sizeof(V);
-  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, op.n_h) +
-               deposit(tile_m, op.a_m + tm, op.n_m - tm);
-  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, op.n_h) +
-               deposit(tile_n, op.b_n + tn, op.n_n - tn);
-  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, op.n_h) +
-         deposit(tile_m, op.c_m + tm, op.n_m - tm) + deposit(tile_n, op.c_n + tn, op.n_n - tn);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, 0, op.n_h) +
+               deposit(tile_m, op.a_m, tm, op.n_m - tm);
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, 0, op.n_h) +
+               deposit(tile_n, op.b_n, tn, op.n_n - tn);
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, 0, op.n_h) +
+         deposit(tile_m, op.c_m, tm, op.n_m - tm) + deposit(tile_n, op.c_n, tn, op.n_n - tn);
   TileMap ma, mb;
   make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
   make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
@@ -949,19 +775,17 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   int a_dst[LA], b_dst[LB];
   for (int i = 0; i < LA; i++) {
     const int e = tid + 256 * i;
-    uint64_t off = 0;
-    int d = 0;
-    for (int b = 0; b < ma.nbits; b++)
-      if ((e >> b) & 1) { off |= uint64_t(1) << ma.pos[b]; d |= 1 << ma.dst[b]; }
+    uint64_t off;
+    int d;
+    tile_elem(ma, e, off, d);
     a_off[i] = off;
     a_dst[i] = (e >> ma.nbits) == 0 ? d : -1;
   }
   for (int i = 0; i < LB; i++) {
     const int e = tid + 256 * i;
-    uint64_t off = 0;
-    int d = 0;
-    for (int b = 0; b < mb.nbits; b++)
-      if ((e >> b) & 1) { off |= uint64_t(1) << mb.pos[b]; d |= 1 << mb.dst[b]; }
+    uint64_t off;
+    int d;
+    tile_elem(mb, e, off, d);
     b_off[i] = off;
     b_dst[i] = (e >> mb.nbits) == 0 ? d : -1;
   }
@@ -973,8 +797,8 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
     for (int j = 0; j < 4; j++) { acc[i][j].x = 0; acc[i][j].y = 0; }
   const uint64_t nsteps = uint64_t(1) << (op.n_k - tk);
   for (uint64_t s = 0; s < nsteps; s++) {
-    const uint64_t ka = deposit(s, op.a_k + tk, op.n_k - tk);
-    const uint64_t kb = deposit(s, op.b_k + tk, op.n_k - tk);
+    const uint64_t ka = deposit(s, op.a_k, tk, op.n_k - tk);
+    const uint64_t kb = deposit(s, op.b_k, tk, op.n_k - tk);
     __syncthreads();
     for (int i = 0; i < LA; i++)
       if (a_dst[i] >= 0) (&As[0][0])[(a_dst[i] >> RM) * BM + (a_dst[i] & (BM - 1))] = conjv(ld(A + ka + a_off[i]), op.conj_a);
@@ -993,11 +817,11 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   for (int i = 0; i < 4; i++) {
     const int row = ty + 16 * i;
     if (row >= mvalid) continue;
-    const uint64_t ro = deposit(row, op.c_m, tm);
+    const uint64_t ro = deposit(row, op.c_m, 0, tm);
     for (int j = 0; j < 4; j++) {
       const int col = tx + 16 * j;
       if (col >= nvalid) continue;
-      GMEM V* d = C + ro + deposit(col, op.c_n, tn);
+      GMEM V* d = C + ro + deposit(col, op.c_n, 0, tn);
       if (op.accumulate) { V o = ld(d); o.x += acc[i][j].x; o.y += acc[i][j].y; st(d, o); }
       else st(d, acc[i][j]);
     }

@@ -405,10 +405,19 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     }
     for (int i = 0; i < fb; i++) { r.in_c[i] = (int8_t)posC(FB[i]); r.in_b[i] = (int8_t)B.lay.pos_of(FB[i]); }
     for (int i = 0; i < k; i++) { r.k_a[i] = (int8_t)A.lay.pos_of(K[i]); r.k_b[i] = (int8_t)B.lay.pos_of(K[i]); }
+    // paired 16-byte accesses where the lowest bit of the run sits at
+    // position 0 and no slice offset can make the base odd
+    auto even_base = [](const Ref& rf) {
+      for (int i = 0; i < rf.n_slice; i++)
+        if (rf.slice_pos[i] == 0) return false;
+      return true;
+    };
+    r.pair_a = (k >= 1 && r.k_a[0] == 0 && even_base(r.a) && p->elem_bytes == 8) ? 1 : 0;
+    r.pair_c = (fb >= 1 && r.in_c[0] == 0 && even_base(r.c) && p->elem_bytes == 8) ? 1 : 0;
     // few rows and a long sum: lanes stride over K, chunks reduced in order
     int nrows = r.n_rows;
     if (nrows < 14 && k >= 6) {
-      int ks = std::min(k - 6, std::max(0, 11 - nrows));
+      int ks = std::min(k - 6, std::max(0, 13 - nrows));
       r.k_split_bits = ks;
       op.grid_rows = int64_t(1) << (nrows + ks);
       if (ks > 0) {
@@ -541,8 +550,8 @@ static int classes(tn_plan_s* p, std::string& err) {
       }
     for (int b : KR)
       if (!contains(KV, b) && !contains(KL, b)) { err = "internal: summed bit on one child only"; return TN_E_INVALID; }
-    if (KV.size() > 62 || KL.size() > 62 || KR.size() > 62) {
-      err = "a tensor has more than 62 binary axes after slicing";
+    if (KV.size() > 32 || KL.size() > 32 || KR.size() > 32) {
+      err = "a tensor has more than 2^32 elements after slicing (slice more indices)";
       return TN_E_UNSUPPORTED;
     }
     if (ni.K.size() > (size_t)kMaxBits || (ni.H.size() + std::max(ni.M.size(), ni.N.size())) > (size_t)kMaxBits ||

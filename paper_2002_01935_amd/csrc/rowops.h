@@ -1,0 +1,378 @@
+// Element helpers, operand addressing and the bandwidth-class contraction
+// kernels (row, split-K, split-K reduction).  Included inside namespace tn by
+// kernels.hip; written in plain C++ over a few HIP names (__global__,
+// __device__, threadIdx / blockIdx / blockDim, __shfl_xor, the GMEM address
+// space tag) so that the same source can also be compiled for the host with
+// stand-ins for those names and run on the CPU in tests.
+#pragma once
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T> struct C2;
+template <> struct C2<float> { using t = float2; };
+template <> struct C2<double> { using t = double2; };
+
+template <typename V> struct Scal;
+template <> struct Scal<float2> { using t = float; };
+template <> struct Scal<double2> { using t = double; };
+
+// element load / store through the native two-lane vector type
+template <typename V>
+__device__ __forceinline__ V ld(GMEM const V* p) {
+  typedef typename Scal<V>::t T;
+  typedef T n2 __attribute__((ext_vector_type(2)));
+  const n2 v = *reinterpret_cast<GMEM const n2*>(p);
+  V r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+template <typename V>
+__device__ __forceinline__ void st(GMEM V* p, V v) {
+  typedef typename Scal<V>::t T;
+  typedef T n2 __attribute__((ext_vector_type(2)));
+  n2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *reinterpret_cast<GMEM n2*>(p) = w;
+}
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+template <typename V>
+__device__ __forceinline__ V cfma(V acc, V a, V b) {
+  acc.x = acc.x + a.x * b.x - a.y * b.y;
+  acc.y = acc.y + a.x * b.y + a.y * b.x;
+  return acc;
+}
+
+// Entry i of a bit-position list.  `base` is the start of an int8 list in a
+// 4-byte aligned op struct of the kernel arguments; reading the containing
+// dword keeps the load a uniform scalar load (there are no scalar byte loads).
+__device__ __forceinline__ int pos_at(const int8_t* base, int i) {
+  const uint32_t w = reinterpret_cast<const uint32_t*>(base)[i >> 2];
+  return (int8_t)(w >> (8 * (i & 3)));
+}
+
+// The deposits are branch-free, so the position reads stay uniform even when
+// v differs between lanes.
+__device__ __forceinline__ uint64_t deposit(uint64_t v, const int8_t* pos, int first, int n) {
+  uint64_t off = 0;
+  for (int i = 0; i < n; i++) off |= ((v >> i) & 1) << pos_at(pos, first + i);
+  return off;
+}
+
+// position list may hold -1 (bit absent from this operand)
+__device__ __forceinline__ uint64_t deposit_opt(uint64_t v, const int8_t* pos, int first, int n) {
+  uint64_t off = 0;
+  for (int i = 0; i < n; i++) {
+    const int p = pos_at(pos, first + i);
+    off |= p >= 0 ? ((v >> i) & 1) << p : 0;
+  }
+  return off;
+}
+
+// The batch counter, the slice-id list and the pointer table are read at
+// uniform addresses and do not change while a kernel runs: reading them
+// through the constant address space (CMEM) makes these scalar loads instead
+// of a chain of dependent vector loads at the start of every wavefront.
+__device__ __forceinline__ int64_t slice_id(const Ctx& ctx, int z) {
+  const int64_t cnt = *reinterpret_cast<CMEM const int64_t*>(ctx.ws + ctx.counter_off);
+  CMEM const int64_t* sids = reinterpret_cast<CMEM const int64_t*>(ctx.ws + ctx.sid_off);
+  return sids[cnt * ctx.n_batch + z];
+}
+
+// Base address of an operand for in-flight slice z with slice id sid.
+__device__ __forceinline__ GMEM char* resolve(const Ctx& ctx, const Ref& r, int z, int64_t sid, int ebytes) {
+  if (r.kind == 1)
+    return reinterpret_cast<GMEM char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
+  const uint64_t p = reinterpret_cast<CMEM const uint64_t*>(ctx.ws + ctx.ptrtab_off)[r.slot];
+  uint64_t off = 0;
+  for (int i = 0; i < r.n_slice; i++) {
+    const uint32_t wb = reinterpret_cast<const uint32_t*>(r.slice_bit)[i >> 2];
+    const uint32_t wp = reinterpret_cast<const uint32_t*>(r.slice_pos)[i >> 2];
+    const int sh = 8 * (i & 3);
+    off |= uint64_t((sid >> ((wb >> sh) & 0xFF)) & 1) << ((wp >> sh) & 0xFF);
+  }
+  return reinterpret_cast<GMEM char*>(p) + off * uint64_t(ebytes);
+}
+
+template <typename V>
+__device__ __forceinline__ V conjv(V a, int c) {
+  if (c) a.y = -a.y;
+  return a;
+}
+
+// ------------------------------------------------------------------ row kernel
+
+constexpr int kRowThreads = 256;
+
+// Offsets below are 32-bit: the planner rejects tensors of 2^32 elements or more.
+__device__ __forceinline__ uint32_t dep32(uint32_t v, const int8_t* pos, int first, int n) {
+  uint32_t off = 0;
+  for (int i = 0; i < n; i++) off |= ((v >> i) & 1u) << pos_at(pos, first + i);
+  return off;
+}
+__device__ __forceinline__ uint32_t dep32_opt(uint32_t v, const int8_t* pos, int first, int n) {
+  uint32_t off = 0;
+  for (int i = 0; i < n; i++) {
+    const int p = pos_at(pos, first + i);
+    off |= p >= 0 ? ((v >> i) & 1u) << p : 0u;
+  }
+  return off;
+}
+// Offset change of a counter going from c to c + 1 when its bit i sits at
+// position pos[first + i] of an operand: the trailing ones of c clear and the
+// next bit sets.  Two operands walked by the same counter may order their bits
+// differently, so each takes its own delta; c is uniform, so this is scalar
+// work (two iterations on average).  Call only while c + 1 is in range.
+__device__ __forceinline__ uint64_t step_delta(uint64_t c, const int8_t* pos, int first) {
+  const int t = __builtin_ctzll(~c);
+  uint64_t d = uint64_t(1) << pos_at(pos, first + t);
+  for (int b = 0; b < t; b++) d -= uint64_t(1) << pos_at(pos, first + b);
+  return d;
+}
+
+// One thread per row; the summed bits are walked in order with their A / B
+// offsets advanced as masked counters, and a batch of A loads (and the B
+// loads that go with them) is issued before any of it is used, so that each
+// thread keeps several memory requests in flight.
+template <typename T, int NIN>
+__global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  constexpr int LB = 8;                       // log2 kRowThreads: row bits that vary within a block
+  constexpr int KU = NIN <= 2 ? 8 : (NIN <= 4 ? 4 : 2);
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + tid;
+  if (row >> op.n_rows) return;
+  const int eb = sizeof(V);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
+  // row = block bits (uniform) | thread bits
+  const int nl = op.n_rows < LB ? op.n_rows : LB;
+  const uint32_t blk = blockIdx.x;
+  const uint32_t oa = dep32_opt(blk, op.row_a, LB, op.n_rows - nl) + dep32_opt(tid, op.row_a, 0, nl);
+  const uint32_t ob = dep32_opt(blk, op.row_b, LB, op.n_rows - nl) + dep32_opt(tid, op.row_b, 0, nl);
+  const uint32_t oc = dep32(blk, op.row_c, LB, op.n_rows - nl) + dep32(tid, op.row_c, 0, nl);
+  uint32_t inb[NIN], inc[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { inb[j] = dep32(j, op.in_b, 0, op.n_in); inc[j] = dep32(j, op.in_c, 0, op.n_in); }
+  V acc[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { acc[j].x = 0; acc[j].y = 0; }
+  const uint32_t nk = 1u << op.n_k;
+  if (op.pair_a) {
+    // k and k + 1 are adjacent in A: one 16-byte load for both; the counter
+    // runs over the summed bits above the lowest
+    const uint32_t b1 = 1u << pos_at(op.k_b, 0);
+    uint32_t xa = 0, xb = 0;
+    for (uint32_t k = 0; k < nk; k += 2 * KU) {
+      t4 a2[KU];
+      uint32_t bo[KU];
+#pragma unroll
+      for (int u = 0; u < KU; u++)
+        if (k + 2 * u < nk) {
+          a2[u] = *reinterpret_cast<GMEM const t4*>(A + oa + xa);
+          bo[u] = ob + xb;
+          const uint32_t c = (k >> 1) + u;      // counter over the summed bits above the lowest
+          if (2 * (c + 1) < nk) {
+            xa += (uint32_t)step_delta(c, op.k_a, 1);
+            xb += (uint32_t)step_delta(c, op.k_b, 1);
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < KU; u++)
+        if (k + 2 * u < nk) {
+          V a0, a1;
+          a0.x = a2[u][0];
+          a0.y = op.conj_a ? -a2[u][1] : a2[u][1];
+          a1.x = a2[u][2];
+          a1.y = op.conj_a ? -a2[u][3] : a2[u][3];
+#pragma unroll
+          for (int j = 0; j < NIN; j++) {
+            acc[j] = cfma(acc[j], a0, conjv(ld(B + bo[u] + inb[j]), op.conj_b));
+            acc[j] = cfma(acc[j], a1, conjv(ld(B + bo[u] + b1 + inb[j]), op.conj_b));
+          }
+        }
+    }
+  } else {
+    uint32_t xa = 0, xb = 0;
+    for (uint32_t k = 0; k < nk; k += KU) {
+      V a[KU];
+      uint32_t bo[KU];
+#pragma unroll
+      for (int u = 0; u < KU; u++)
+        if (k + u < nk) {
+          a[u] = conjv(ld(A + oa + xa), op.conj_a);
+          bo[u] = ob + xb;
+          if (k + u + 1 < nk) {
+            xa += (uint32_t)step_delta(k + u, op.k_a, 0);
+            xb += (uint32_t)step_delta(k + u, op.k_b, 0);
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < KU; u++)
+        if (k + u < nk) {
+#pragma unroll
+          for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a[u], conjv(ld(B + bo[u] + inb[j]), op.conj_b));
+        }
+    }
+  }
+  if (op.accumulate) {
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      V o = ld(Cp + oc + inc[j]);
+      acc[j].x += o.x;
+      acc[j].y += o.y;
+    }
+  }
+  if (NIN >= 2 && op.pair_c) {
+    // in-thread values j and j + 1 are adjacent in C
+#pragma unroll
+    for (int j = 0; j < NIN; j += 2) {
+      t4 w;
+      w[0] = acc[j].x;
+      w[1] = acc[j].y;
+      w[2] = acc[j + 1].x;
+      w[3] = acc[j + 1].y;
+      *reinterpret_cast<GMEM t4*>(Cp + oc + inc[j]) = w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NIN; j++) st(Cp + oc + inc[j], acc[j]);
+  }
+}
+
+// ------------------------------------------------------------------ split-K
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  // fixed butterfly order: identical result on every run
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wavefront per (row, chunk of the summed range): lane l takes
+// k = chunk * 2^cbits + 64 t + l for t = 0, 1, ..., so every load of the
+// wavefront covers 64 consecutive k; the lane bits of the offset are fixed
+// and the bits above advance as a masked counter.  Partial sums of the lanes
+// are combined by a fixed butterfly.
+template <typename T, int NIN>
+__global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  constexpr int KU = NIN <= 2 ? 8 : (NIN <= 4 ? 4 : 2);
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+  const uint32_t row = (uint32_t)(wave >> ks);
+  const uint32_t chunk = (uint32_t)(wave & ((uint64_t(1) << ks) - 1));
+  if ((wave >> ks) >> op.n_rows) return;
+  const int eb = sizeof(V);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
+  const int cbits = op.n_k - ks;                  // >= 6
+  const uint32_t ba = dep32_opt(row, op.row_a, 0, op.n_rows) + dep32(chunk, op.k_a, cbits, ks) + dep32(lane, op.k_a, 0, 6);
+  const uint32_t bb = dep32_opt(row, op.row_b, 0, op.n_rows) + dep32(chunk, op.k_b, cbits, ks) + dep32(lane, op.k_b, 0, 6);
+  uint32_t inb[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) inb[j] = dep32(j, op.in_b, 0, op.n_in);
+  T ar[NIN], ai[NIN];
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { ar[j] = 0; ai[j] = 0; }
+  const uint32_t steps = 1u << (cbits - 6);
+  uint32_t xa = 0, xb = 0;
+  for (uint32_t t = 0; t < steps; t += KU) {
+    V a[KU];
+    uint32_t bo[KU];
+#pragma unroll
+    for (int u = 0; u < KU; u++)
+      if (t + u < steps) {
+        a[u] = conjv(ld(A + ba + xa), op.conj_a);
+        bo[u] = bb + xb;
+        if (t + u + 1 < steps) {
+          xa += (uint32_t)step_delta(t + u, op.k_a, 6);
+          xb += (uint32_t)step_delta(t + u, op.k_b, 6);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < KU; u++)
+      if (t + u < steps) {
+#pragma unroll
+        for (int j = 0; j < NIN; j++) {
+          const V b = conjv(ld(B + bo[u] + inb[j]), op.conj_b);
+          ar[j] += a[u].x * b.x - a[u].y * b.y;
+          ai[j] += a[u].x * b.y + a[u].y * b.x;
+        }
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < NIN; j++) { ar[j] = wave_sum(ar[j]); ai[j] = wave_sum(ai[j]); }
+  if (lane != 0) return;
+  if (ks == 0) {
+    GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
+    const uint32_t oc = dep32(row, op.row_c, 0, op.n_rows);
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      const uint32_t c = oc + dep32(j, op.in_c, 0, op.n_in);
+      V o;
+      o.x = ar[j];
+      o.y = ai[j];
+      if (op.accumulate) { V p = ld(Cp + c); o.x += p.x; o.y += p.y; }
+      st(Cp + c, o);
+    }
+  } else {
+    GMEM V* P = reinterpret_cast<GMEM V*>(resolve(ctx, op.part, z, sid, eb));
+    const uint64_t base = ((uint64_t(chunk) << op.n_rows) + row) * NIN;
+#pragma unroll
+    for (int j = 0; j < NIN; j++) {
+      V o;
+      o.x = ar[j];
+      o.y = ai[j];
+      st(P + base + j, o);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) {
+  using V = typename C2<T>::t;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int nin = 1 << op.n_in;
+  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t row = t / nin;
+  const int j = (int)(t % nin);
+  if (row >> op.n_rows) return;
+  const int eb = sizeof(V);
+  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, eb));
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
+  V s;
+  s.x = 0;
+  s.y = 0;
+  const uint64_t nch = uint64_t(1) << op.k_split_bits;
+  for (uint64_t ch = 0; ch < nch; ch++) {
+    const V p = ld(P + ((ch << op.n_rows) + row) * nin + j);
+    s.x += p.x;
+    s.y += p.y;
+  }
+  const uint64_t c = deposit(row, op.row_c, 0, op.n_rows) + deposit(j, op.in_c, 0, op.n_in);
+  if (op.accumulate) { V p = ld(Cp + c); s.x += p.x; s.y += p.y; }
+  st(Cp + c, s);
+}

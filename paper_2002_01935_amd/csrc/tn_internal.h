@@ -10,6 +10,7 @@
 // the consuming node asks for.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace tn {
@@ -57,6 +58,8 @@ struct RowOp {
   int32_t k_split_bits;    // log2 number of K chunks (split-K mode); -1 = row mode
   int32_t conj_a, conj_b;
   int32_t accumulate;      // add into C instead of overwriting
+  int32_t pair_a;          // A's lowest summed bit sits at position 0 and A's base is pair-aligned: 16-byte loads over k
+  int32_t pair_c;          // C's lowest in-thread bit sits at position 0: 16-byte stores over the in-thread values
   int8_t row_c[kMaxBits], row_a[kMaxBits], row_b[kMaxBits];
   int8_t in_c[kMaxInThread], in_b[kMaxInThread];
   int8_t k_a[kMaxBits], k_b[kMaxBits];
@@ -96,5 +99,13 @@ struct PermuteOp {
   int32_t per_slice_serial;// accumulate the in-flight slices one after another (deterministic)
   int8_t src_pos[kMaxBits], dst_pos[kMaxBits];
 };
+
+// Device code reads the int8 position lists a dword at a time: every op
+// struct must be 4-byte aligned with a size that is a multiple of 4.
+static_assert(offsetof(Ref, slice_bit) % 4 == 0 && offsetof(Ref, slice_pos) % 4 == 0, "Ref layout");
+static_assert(alignof(RowOp) >= 4 && sizeof(RowOp) % 4 == 0, "RowOp layout");
+static_assert(alignof(GemmOp) >= 4 && sizeof(GemmOp) % 4 == 0, "GemmOp layout");
+static_assert(alignof(PermuteOp) >= 4 && sizeof(PermuteOp) % 4 == 0, "PermuteOp layout");
+static_assert(alignof(AccumOp) >= 4 && sizeof(AccumOp) % 4 == 0, "AccumOp layout");
 
 }  // namespace tn

@@ -1,0 +1,211 @@
+// Host build of the row / split-K / reduce kernels (csrc/rowops.h) with
+// stand-ins for the HIP names they use, driven by the real planner
+// (csrc/plan.cpp): plans a network read from a text file, runs the forward
+// program's ops on the CPU (one host thread per lane for split-K wavefronts,
+// whose lane sums need the cross-lane shuffle), and writes the root of each
+// requested slice.  Test infrastructure: used by tests/test_kernel_emulation.py.
+//
+// usage: emu_rowops NET.txt LEAVES.bin OUT.bin
+//   NET.txt: n_leaves n_idx n_out prec / ranks / leaf indices / dims / out / left / right /
+//            n_sliced sliced... / n_ids ids...
+//   LEAVES.bin: complex128 leaves, row-major; OUT.bin: complex128 roots (out order), one per id
+// exit code 3: the plan holds an op kind the emulator does not run (matrix-core GEMM)
+#include <barrier>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <complex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "plan.h"
+
+struct float2 { float x, y; };
+struct double2 { double x, y; };
+struct Dim3 { unsigned x, y, z; };
+static thread_local Dim3 threadIdx, blockIdx, blockDim;
+#define __global__
+#define __device__
+#define __forceinline__ inline
+#define __launch_bounds__(x)
+#define GMEM
+#define CMEM
+
+static std::barrier<>* g_wave_barrier = nullptr;
+static double g_lane_value[64];
+template <typename T>
+static T __shfl_xor(T v, int mask, int) {
+  const int l = threadIdx.x & 63;
+  g_lane_value[l] = (double)v;
+  g_wave_barrier->arrive_and_wait();
+  const T r = (T)g_lane_value[l ^ mask];
+  g_wave_barrier->arrive_and_wait();
+  return r;
+}
+
+namespace tn {
+#include "rowops.h"
+}
+using namespace tn;
+
+template <typename T>
+static void run_row(const Ctx& ctx, const RowOp& op, int z) {
+  const uint64_t rows = 1ull << op.n_rows;
+  const unsigned nblk = (unsigned)((rows + kRowThreads - 1) / kRowThreads);
+  for (unsigned b = 0; b < nblk; b++)
+    for (unsigned t = 0; t < (unsigned)kRowThreads; t++) {
+      blockDim = {(unsigned)kRowThreads, 1, 1};
+      blockIdx = {b, (unsigned)z, 0};
+      threadIdx = {t, 0, 0};
+      switch (op.n_in) {
+        case 0: row_kernel<T, 1>(ctx, op); break;
+        case 1: row_kernel<T, 2>(ctx, op); break;
+        case 2: row_kernel<T, 4>(ctx, op); break;
+        case 3: row_kernel<T, 8>(ctx, op); break;
+        default: row_kernel<T, 16>(ctx, op); break;
+      }
+    }
+}
+
+// 64 host threads play the lanes of one wavefront at a time; the shuffles
+// and the end of each wavefront synchronise them.
+template <typename T>
+static void run_splitk(const Ctx& ctx, const RowOp& op, int64_t waves, int z) {
+  const int wpb = kRowThreads / 64;
+  std::barrier<> bar(64);
+  g_wave_barrier = &bar;
+  std::vector<std::thread> lanes;
+  for (int l = 0; l < 64; l++)
+    lanes.emplace_back([&, l] {
+      for (int64_t w = 0; w < waves; w++) {
+        blockDim = {(unsigned)kRowThreads, 1, 1};
+        blockIdx = {(unsigned)(w / wpb), (unsigned)z, 0};
+        threadIdx = {(unsigned)((w % wpb) * 64 + l), 0, 0};
+        switch (op.n_in) {
+          case 0: splitk_kernel<T, 1>(ctx, op); break;
+          case 1: splitk_kernel<T, 2>(ctx, op); break;
+          case 2: splitk_kernel<T, 4>(ctx, op); break;
+          case 3: splitk_kernel<T, 8>(ctx, op); break;
+          default: splitk_kernel<T, 16>(ctx, op); break;
+        }
+        bar.arrive_and_wait();
+      }
+    });
+  for (auto& t : lanes) t.join();
+}
+
+template <typename T>
+static void run_reduce(const Ctx& ctx, const RowOp& op, int z) {
+  const uint64_t n = 1ull << (op.n_rows + op.n_in);
+  const unsigned nblk = (unsigned)((n + kRowThreads - 1) / kRowThreads);
+  for (unsigned b = 0; b < nblk; b++)
+    for (unsigned t = 0; t < (unsigned)kRowThreads; t++) {
+      blockDim = {(unsigned)kRowThreads, 1, 1};
+      blockIdx = {b, (unsigned)z, 0};
+      threadIdx = {t, 0, 0};
+      reduce_kernel<T>(ctx, op);
+    }
+}
+
+int main(int argc, char** argv) {
+  if (argc != 4) return 1;
+  FILE* f = fopen(argv[1], "r");
+  if (!f) return 1;
+  int nl, nidx, nout, prec;
+  if (fscanf(f, "%d %d %d %d", &nl, &nidx, &nout, &prec) != 4) return 1;
+  tn_plan_s* p = new tn_plan_s();
+  p->n_leaves = nl;
+  p->n_idx = nidx;
+  p->n_out = nout;
+  int tot = 0;
+  for (int v = 0; v < nl; v++) { int r; fscanf(f, "%d", &r); p->rank.push_back(r); tot += r; }
+  for (int i = 0; i < tot; i++) { long x; fscanf(f, "%ld", &x); p->leaf_idx.push_back(x); }
+  for (int i = 0; i < nidx; i++) { long x; fscanf(f, "%ld", &x); p->idx_dim.push_back(x); }
+  for (int i = 0; i < nout; i++) { long x; fscanf(f, "%ld", &x); p->out_idx.push_back(x); }
+  for (int i = 0; i < nl - 1; i++) { int x; fscanf(f, "%d", &x); p->left.push_back(x); }
+  for (int i = 0; i < nl - 1; i++) { int x; fscanf(f, "%d", &x); p->right.push_back(x); }
+  int ns;
+  fscanf(f, "%d", &ns);
+  p->n_sliced = ns;
+  for (int i = 0; i < ns; i++) { long x; fscanf(f, "%ld", &x); p->sliced.push_back(x); }
+  int nids;
+  fscanf(f, "%d", &nids);
+  std::vector<int64_t> ids(nids);
+  for (int i = 0; i < nids; i++) { long x; fscanf(f, "%ld", &x); ids[i] = x; }
+  fclose(f);
+  p->opt.prec = (tn_precision)prec;
+  p->prec = p->opt.prec;
+  p->elem_bytes = prec == TN_C128 ? 16 : 8;
+  std::string err;
+  if (build_plan(p, err)) { fprintf(stderr, "plan: %s\n", err.c_str()); return 2; }
+  for (const Op& op : p->fwd)
+    if (op.kind != OpKind::Row && op.kind != OpKind::RowReduce) return 3;
+  const int eb = p->elem_bytes;
+  // leaves, each in its own exactly sized buffer
+  std::vector<std::vector<char>> leaves(nl);
+  FILE* fb = fopen(argv[2], "rb");
+  int off = 0;
+  for (int v = 0; v < nl; v++) {
+    size_t n = 1;
+    for (int i = 0; i < p->rank[v]; i++) n *= p->idx_dim[p->leaf_idx[off + i]];
+    off += p->rank[v];
+    std::vector<std::complex<double>> buf(n);
+    if (fread(buf.data(), 16, n, fb) != n) return 1;
+    leaves[v].resize(n * eb);
+    for (size_t i = 0; i < n; i++) {
+      if (eb == 8) {
+        float* q = reinterpret_cast<float*>(leaves[v].data());
+        q[2 * i] = (float)buf[i].real();
+        q[2 * i + 1] = (float)buf[i].imag();
+      } else {
+        double* q = reinterpret_cast<double*>(leaves[v].data());
+        q[2 * i] = buf[i].real();
+        q[2 * i + 1] = buf[i].imag();
+      }
+    }
+  }
+  fclose(fb);
+  std::vector<char> ws(p->arena_off + p->arena_bytes + 512);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws.data()) + 255) & ~uintptr_t(255));
+  uint64_t* tab = reinterpret_cast<uint64_t*>(base + p->ptrtab_off);
+  for (int v = 0; v < nl; v++) tab[v] = reinterpret_cast<uint64_t>(leaves[v].data());
+  Ctx ctx;
+  std::memset(&ctx, 0, sizeof ctx);
+  ctx.ws = reinterpret_cast<uint64_t>(base);
+  ctx.arena_stride = p->arena_bytes;
+  ctx.ptrtab_off = p->ptrtab_off;
+  ctx.sid_off = p->sid_off;
+  ctx.counter_off = p->counter_off;
+  ctx.arena_off = p->arena_off;
+  ctx.n_batch = 1;
+  ctx.elem_bytes = eb;
+  size_t nout_el = 1;
+  for (int i = 0; i < nout; i++) nout_el *= p->idx_dim[p->out_idx[i]];
+  FILE* fo = fopen(argv[3], "wb");
+  for (int64_t sid : ids) {
+    *reinterpret_cast<int64_t*>(base + p->counter_off) = 0;
+    *reinterpret_cast<int64_t*>(base + p->sid_off) = sid;
+    for (const Op& op : p->fwd) {
+      if (op.kind == OpKind::RowReduce) {
+        if (eb == 8) run_reduce<float>(ctx, op.row, 0); else run_reduce<double>(ctx, op.row, 0);
+      } else if (op.row.k_split_bits >= 0) {
+        if (eb == 8) run_splitk<float>(ctx, op.row, op.grid_rows, 0); else run_splitk<double>(ctx, op.row, op.grid_rows, 0);
+      } else {
+        if (eb == 8) run_row<float>(ctx, op.row, 0); else run_row<double>(ctx, op.row, 0);
+      }
+    }
+    const char* root = base + p->arena_off + p->root_off;
+    for (size_t i = 0; i < nout_el; i++) {
+      double re, im;
+      if (eb == 8) { re = reinterpret_cast<const float*>(root)[2 * i]; im = reinterpret_cast<const float*>(root)[2 * i + 1]; }
+      else { re = reinterpret_cast<const double*>(root)[2 * i]; im = reinterpret_cast<const double*>(root)[2 * i + 1]; }
+      fwrite(&re, 8, 1, fo);
+      fwrite(&im, 8, 1, fo);
+    }
+  }
+  fclose(fo);
+  delete p;
+  return 0;
+}
