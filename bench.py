@@ -42,6 +42,8 @@ WORKLOADS = {
     "cfg3": "7x7 grid circuit (49 qubits), 14 cycles, one amplitude, sliced to W_s=27, seeded slice ids",
     "cfg2": "random 3-regular graph, 120 rank-3 tensors, bond 2, sliced to W_s=20, all slices",
     "cfg4": "6x6 grid circuit (36 qubits), 12 cycles, one amplitude, W=28, unsliced",
+    "cfg5h": "cfg5 circuit with every fSim written as SWAP times a diagonal gate (hyperedge wires, batched "
+             "contractions), 64 amplitudes, sliced to W_s=30, seeded slice ids",
 }
 
 
@@ -282,6 +284,44 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 4, "dispatches": 3}))
 
 
+def adjoint_bench(precision, torch, np, Plan, configs, reps=3):
+    """Reverse mode on cfg4 (6x6 grid, 12 cycles, width 28): the amplitude c,
+    then dL/dconj(G) of L = |c|^2 for all 180 fSim leaves through
+    tn_contract_backward (recomputation from checkpoints).  Times are medians of
+    `reps` warm calls; FLOPs are the planner's 8C counts of the forward and of
+    the backward program (recomputation included)."""
+    from tn_inputs.circuits import gate_leaves
+    net, tree, sliced = configs.load("cfg4")
+    plan = Plan(net, tree, sliced=sliced, precision=precision)
+    wrt = gate_leaves(net, "2q")
+    binfo = plan.backward_info(wrt)
+    ws = plan.workspace(max(binfo["workspace_bytes"], plan.info()["workspace_bytes"]))
+    plan.tune(ws)
+    leaves = [torch.from_numpy(np.ascontiguousarray(t)).to("cuda", plan.storage_dtype) for t in net.leaves]
+    grads = [torch.empty(plan.leaf_shapes[v], dtype=plan.storage_dtype, device="cuda") for v in wrt]
+    out = torch.empty(plan.out_shape, dtype=torch.complex128, device="cuda")
+    tf, tb = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = plan.contract_sliced(leaves, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.backward(leaves, (2 * c).reshape(()), wrt, grads=grads, workspace=ws)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r:
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+    f_fl = plan.info()["flops_per_slice"] * plan.info()["d_sliced"]
+    b_fl = binfo["flops_per_slice"] * plan.info()["d_sliced"]
+    tfm, tbm = sorted(tf)[len(tf) // 2], sorted(tb)[len(tb) // 2]
+    return {"workload": "cfg4: 6x6 grid circuit, 12 cycles, one amplitude, W=28; d|amp|^2/d(all 180 fSim leaves)",
+            "precision": precision, "forward_s": round(tfm, 4), "backward_s": round(tbm, 4),
+            "forward_tflops": round(f_fl / tfm / 1e12, 2), "backward_tflops": round(b_fl / tbm / 1e12, 2),
+            "backward_over_forward_flops": round(b_fl / f_fl, 2), "n_grads": len(wrt)}
+
+
 def node_bench(spec, precision, reps):
     """One pairwise contraction node, A[M][K] x B[N][K] -> C[M][N] (binary
     indices, canonical layouts, seeded complex normal entries), timed per
@@ -341,6 +381,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-timed-pass", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the cfg4 forward + backward timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sliced contraction is measured on a single MI355X "
@@ -479,6 +520,16 @@ def main():
             del vws, vp
             torch.cuda.empty_cache()
 
+    adjoint = None
+    if not args.no_adjoint and args.precision in ("c64_4m", "c64_3m", "c64_bf16x3"):
+        try:
+            del ws
+        except NameError:
+            pass
+        torch.cuda.empty_cache()
+        adjoint = adjoint_bench(args.precision, torch, np, Plan, configs)
+        log(f"adjoint (cfg4): {adjoint}")
+
     res = {
         "metric": "TFLOP/s on contraction tree + s/amplitude at stated error vs FP64, vs plain path",
         "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -490,7 +541,7 @@ def main():
                    "flops_8C_per_slice": info["flops_per_slice"], "amplitudes": n_amps},
         "s_per_slice": round(per_slice, 4),
         "s_per_amplitude_extrapolated": round(per_slice * info["d_sliced"] / n_amps, 4),
-        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain, "variants": variants,
+        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain, "variants": variants, "adjoint": adjoint,
     }
     print(json.dumps(res), flush=True)
 

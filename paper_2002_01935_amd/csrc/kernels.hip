@@ -25,6 +25,8 @@
 //   gemm_valu      tiled vector-ALU complex GEMM, used for complex128.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace tn {
@@ -47,8 +49,8 @@ __global__ __launch_bounds__(256) void permute_kernel(Ctx ctx, PermuteOp op) {
   using VD = typename C2<TD>::t;
   const uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >> op.n_bits) return;
-  const uint64_t so = deposit(e, op.src_pos, 0, op.n_bits);
-  const uint64_t dof = deposit(e, op.dst_pos, 0, op.n_bits);
+  const uint64_t so = deposit_runs(e, op.run_src);
+  const uint64_t dof = deposit_runs(e, op.run_dst);
   const int z0 = op.per_slice_serial ? 0 : blockIdx.y;
   const int z1 = op.per_slice_serial ? ctx.n_batch : blockIdx.y + 1;
   for (int z = z0; z < z1; z++) {
@@ -220,8 +222,8 @@ __device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, con
                                            const floatx16 (&acc)[FM][FN], int wm, int wn, int tid, int nthreads) {
   constexpr int WM = FM * 32, WN = FN * 16;
   GMEM float* C = reinterpret_cast<GMEM float*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit(g.h, op.c_h, 0, op.n_h) + deposit(g.tile_m, op.c_m, g.tm, op.n_m - g.tm) +
-                         deposit(g.tile_n, op.c_n, g.tn, op.n_n - g.tn);
+  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
+                         deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
   for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
@@ -292,9 +294,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
+                         deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
+                         deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -428,9 +430,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
+                         deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
+                         deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -535,8 +537,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 
   // epilogue: lane holds complex column c32 of each 32 x 32 tile
   GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit(g.h, op.c_h, 0, op.n_h) + deposit(g.tile_m, op.c_m, g.tm, op.n_m - g.tm) +
-                         deposit(g.tile_n, op.c_n, g.tn, op.n_n - g.tn);
+  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
+                         deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
   uint64_t* coloff = rowoff + BM;
   for (int i = tid; i < BM; i += NT) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
@@ -602,9 +604,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
   GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit(g.h, op.a_h, 0, op.n_h) + deposit(g.tile_m, op.a_m, g.tm, op.n_m - g.tm);
+                         deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
   GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit(g.h, op.b_h, 0, op.n_h) + deposit(g.tile_n, op.b_n, g.tn, op.n_n - g.tn);
+                         deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
   int16_t a_dst[LA], b_dst[LB];
@@ -761,12 +763,12 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   const uint64_t ntiles_n = uint64_t(1) << (op.n_n - tn);
   const uint64_t tile_m = blockIdx.x / ntiles_n, tile_n = blockIdx.x % ntiles_n;
   const int eb = sizeof(V);
-  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit(h, op.a_h, 0, op.n_h) +
-               deposit(tile_m, op.a_m, tm, op.n_m - tm);
-  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit(h, op.b_h, 0, op.n_h) +
-               deposit(tile_n, op.b_n, tn, op.n_n - tn);
-  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit(h, op.c_h, 0, op.n_h) +
-         deposit(tile_m, op.c_m, tm, op.n_m - tm) + deposit(tile_n, op.c_n, tn, op.n_n - tn);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit_runs(h, op.run_a_h) +
+               deposit_runs(tile_m << tm, op.run_a_m);
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit_runs(h, op.run_b_h) +
+               deposit_runs(tile_n << tn, op.run_b_n);
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit_runs(h, op.run_c_h) +
+         deposit_runs(tile_m << tm, op.run_c_m) + deposit_runs(tile_n << tn, op.run_c_n);
   TileMap ma, mb;
   make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
   make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
@@ -832,45 +834,71 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
 
 static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
+// Summed-range steps per batch of loads: row_ku(NIN), or the whole range when
+// it is shorter (log2 given in ubits).
+template <typename T, int NIN>
+static void launch_row_u(bool splitk, dim3 grid, const Ctx& ctx, const RowOp& op, int ubits, hipStream_t s) {
+  constexpr int KB = row_ku(NIN) == 8 ? 3 : (row_ku(NIN) == 4 ? 2 : 1);
+  const int ub = ubits < KB ? ubits : KB;
+#define TN_ROW_LAUNCH(U)                                                                            \
+  do {                                                                                              \
+    if (splitk) hipLaunchKernelGGL((splitk_kernel<T, NIN, U>), grid, dim3(kRowThreads), 0, s, ctx, op); \
+    else hipLaunchKernelGGL((row_kernel<T, NIN, U>), grid, dim3(kRowThreads), 0, s, ctx, op);          \
+  } while (0)
+  switch (ub) {
+    case 0: TN_ROW_LAUNCH(1); break;
+    case 1: TN_ROW_LAUNCH(2); break;
+    case 2: if constexpr (KB >= 2) TN_ROW_LAUNCH(4); break;
+    default: if constexpr (KB >= 3) TN_ROW_LAUNCH(8); break;
+  }
+#undef TN_ROW_LAUNCH
+}
+
 template <typename T>
 static hipError_t launch_row_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
-  const uint64_t rows = uint64_t(1) << op.n_rows;
-  dim3 grid(blocks_for(rows, kRowThreads), ctx.n_batch);
+  const bool splitk = op.k_split_bits >= 0;
+  uint64_t units;
+  int ubits;
+  if (splitk) {
+    const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+    units = uint64_t(1) << (op.n_rows + ks);                 // wavefronts
+    ubits = op.n_k - ks - 6;                                 // steps of 64 k per lane
+  } else {
+    units = uint64_t(1) << op.n_rows;                        // threads
+    ubits = op.pair_a ? op.n_k - 1 : op.n_k;                 // (paired) k steps per thread
+  }
+  if (ubits < 0) return hipErrorInvalidValue;
+  dim3 grid(blocks_for(units, splitk ? kRowThreads / 64 : kRowThreads), ctx.n_batch);
   switch (op.n_in) {
-    case 0: hipLaunchKernelGGL((row_kernel<T, 1>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 1: hipLaunchKernelGGL((row_kernel<T, 2>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 2: hipLaunchKernelGGL((row_kernel<T, 4>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 3: hipLaunchKernelGGL((row_kernel<T, 8>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 4: hipLaunchKernelGGL((row_kernel<T, 16>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
+    case 0: launch_row_u<T, 1>(splitk, grid, ctx, op, ubits, s); break;
+    case 1: launch_row_u<T, 2>(splitk, grid, ctx, op, ubits, s); break;
+    case 2: launch_row_u<T, 4>(splitk, grid, ctx, op, ubits, s); break;
+    case 3: launch_row_u<T, 8>(splitk, grid, ctx, op, ubits, s); break;
+    case 4: launch_row_u<T, 16>(splitk, grid, ctx, op, ubits, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_splitk_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
-  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
-  const uint64_t waves = uint64_t(1) << (op.n_rows + ks);
-  dim3 grid(blocks_for(waves, kRowThreads / 64), ctx.n_batch);
-  switch (op.n_in) {
-    case 0: hipLaunchKernelGGL((splitk_kernel<T, 1>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 1: hipLaunchKernelGGL((splitk_kernel<T, 2>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 2: hipLaunchKernelGGL((splitk_kernel<T, 4>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 3: hipLaunchKernelGGL((splitk_kernel<T, 8>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    case 4: hipLaunchKernelGGL((splitk_kernel<T, 16>), grid, dim3(kRowThreads), 0, s, ctx, op); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+// The run tables of an op's position lists (filled here, once per launch or
+// graph capture, so every op the planner makes carries them).
+static RowOp with_runs(const RowOp& in) {
+  RowOp op = in;
+  make_runs(op.row_a, op.n_rows, op.run_a);
+  make_runs(op.row_b, op.n_rows, op.run_b);
+  make_runs(op.row_c, op.n_rows, op.run_c);
+  return op;
 }
 
-hipError_t launch_row(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s) {
-  if (op.k_split_bits >= 0) return f64 ? launch_splitk_t<double>(ctx, op, s) : launch_splitk_t<float>(ctx, op, s);
+hipError_t launch_row(const Ctx& ctx, const RowOp& in, bool f64, hipStream_t s) {
+  const RowOp op = with_runs(in);
   return f64 ? launch_row_t<double>(ctx, op, s) : launch_row_t<float>(ctx, op, s);
 }
 
-hipError_t launch_reduce(const Ctx& ctx, const RowOp& op, bool f64, hipStream_t s) {
-  const uint64_t n = uint64_t(1) << (op.n_rows + op.n_in);
-  dim3 grid(blocks_for(n, kRowThreads), ctx.n_batch);
+hipError_t launch_reduce(const Ctx& ctx, const RowOp& in, bool f64, hipStream_t s) {
+  const RowOp op = with_runs(in);
+  const uint64_t n = uint64_t(1) << (op.n_rows + op.n_in);   // outputs, one wavefront each
+  dim3 grid(blocks_for(n, kRowThreads / 64), ctx.n_batch);
   if (f64) hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kRowThreads), 0, s, ctx, op);
   else hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kRowThreads), 0, s, ctx, op);
   return hipGetLastError();
@@ -889,7 +917,15 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
   }
 }
 
-hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s) {
+hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s) {
+  GemmOp op = in;
+  make_runs(op.a_h, op.n_h, op.run_a_h);
+  make_runs(op.b_h, op.n_h, op.run_b_h);
+  make_runs(op.c_h, op.n_h, op.run_c_h);
+  make_runs(op.a_m, op.n_m, op.run_a_m);
+  make_runs(op.c_m, op.n_m, op.run_c_m);
+  make_runs(op.b_n, op.n_n, op.run_b_n);
+  make_runs(op.c_n, op.n_n, op.run_c_n);
   int bm, bn;
   int tile = op.tile;
   if (prec == TN_C128) tile = 4;
@@ -940,7 +976,10 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& op, int prec, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_permute(const Ctx& ctx, const PermuteOp& op, bool f64, hipStream_t s) {
+hipError_t launch_permute(const Ctx& ctx, const PermuteOp& in, bool f64, hipStream_t s) {
+  PermuteOp op = in;
+  make_runs(op.src_pos, op.n_bits, op.run_src);
+  make_runs(op.dst_pos, op.n_bits, op.run_dst);
   const uint64_t n = uint64_t(1) << op.n_bits;
   dim3 grid(blocks_for(n, 256), op.per_slice_serial ? 1 : ctx.n_batch);
   const bool sd = op.src_c128 != 0, dd = op.dst_c128 != 0;

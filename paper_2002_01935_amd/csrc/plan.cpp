@@ -417,7 +417,8 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     // few rows and a long sum: lanes stride over K, chunks reduced in order
     int nrows = r.n_rows;
     if (nrows < 14 && k >= 6) {
-      int ks = std::min(k - 6, std::max(0, 13 - nrows));
+      // about 2^15 wavefronts: several residency rounds, so the last one is a small tail
+      int ks = std::min(k - 6, std::max(0, 15 - nrows));
       r.k_split_bits = ks;
       op.grid_rows = int64_t(1) << (nrows + ks);
       if (ks > 0) {

@@ -28,6 +28,19 @@ __device__ __forceinline__ V ld(GMEM const V* p) {
   return r;
 }
 
+// the same through the constant address space: a uniform address becomes a
+// scalar load
+template <typename V>
+__device__ __forceinline__ V ldc(CMEM const V* p) {
+  typedef typename Scal<V>::t T;
+  typedef T n2 __attribute__((ext_vector_type(2)));
+  const n2 v = *reinterpret_cast<CMEM const n2*>(p);
+  V r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
 template <typename V>
 __device__ __forceinline__ void st(GMEM V* p, V v) {
   typedef typename Scal<V>::t T;
@@ -120,14 +133,28 @@ __device__ __forceinline__ uint32_t dep32(uint32_t v, const int8_t* pos, int fir
   for (int i = 0; i < n; i++) off |= ((v >> i) & 1u) << pos_at(pos, first + i);
   return off;
 }
-__device__ __forceinline__ uint32_t dep32_opt(uint32_t v, const int8_t* pos, int first, int n) {
-  uint32_t off = 0;
-  for (int i = 0; i < n; i++) {
-    const int p = pos_at(pos, first + i);
-    off |= p >= 0 ? ((v >> i) & 1u) << p : 0u;
+
+// Deposit of an index through the runs of its position list: one
+// shift-and-mask per run (the run table is read at uniform addresses).
+__device__ __forceinline__ uint64_t deposit_runs(uint64_t v, const BitRuns& R) {
+  uint64_t off = 0;
+  for (int i = 0; i < R.n; i++) {
+    const uint32_t w = R.r[i];
+    const uint32_t src = w & 0xFF, dst = (w >> 8) & 0xFF, len = w >> 16;
+    off |= ((v >> src) & (~uint64_t(0) >> (64 - len))) << dst;
   }
   return off;
 }
+__device__ __forceinline__ uint32_t deposit_runs32(uint32_t v, const BitRuns& R) {
+  uint32_t off = 0;
+  for (int i = 0; i < R.n; i++) {
+    const uint32_t w = R.r[i];
+    const uint32_t src = w & 0xFF, dst = (w >> 8) & 0xFF, len = w >> 16;
+    off |= ((v >> src) & (~0u >> (32 - len))) << dst;
+  }
+  return off;
+}
+
 // Offset change of a counter going from c to c + 1 when its bit i sits at
 // position pos[first + i] of an operand: the trailing ones of c clear and the
 // next bit sets.  Two operands walked by the same counter may order their bits
@@ -140,16 +167,31 @@ __device__ __forceinline__ uint64_t step_delta(uint64_t c, const int8_t* pos, in
   return d;
 }
 
+// The same for a counter of n bits, also callable at its last value (the
+// carry is clamped to the counter's width; the result is then not used), so
+// that walks need no guard around their loads.
+__device__ __forceinline__ uint64_t step_delta_n(uint64_t c, const int8_t* pos, int first, int n) {
+  int t = __builtin_ctzll(~c);
+  t = t < n ? t : n - 1;
+  if (t < 0) return 0;
+  uint64_t d = uint64_t(1) << pos_at(pos, first + t);
+  for (int b = 0; b < t; b++) d -= uint64_t(1) << pos_at(pos, first + b);
+  return d;
+}
+
+// Steps of a summed-range walk whose loads are issued together (a template
+// parameter chosen on the host: the range is a power of two, so no step is
+// ever predicated and the compiler keeps all of a chunk's loads in flight).
+constexpr int row_ku(int nin) { return nin <= 2 ? 8 : (nin <= 4 ? 4 : 2); }
+
 // One thread per row; the summed bits are walked in order with their A / B
 // offsets advanced as masked counters, and a batch of A loads (and the B
 // loads that go with them) is issued before any of it is used, so that each
 // thread keeps several memory requests in flight.
-template <typename T, int NIN>
+template <typename T, int NIN, int U>
 __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
   using V = typename C2<T>::t;
   typedef T t4 __attribute__((ext_vector_type(4)));
-  constexpr int LB = 8;                       // log2 kRowThreads: row bits that vary within a block
-  constexpr int KU = NIN <= 2 ? 8 : (NIN <= 4 ? 4 : 2);
   const int z = blockIdx.y;
   const int64_t sid = slice_id(ctx, z);
   if (sid < 0) return;
@@ -160,12 +202,10 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
   GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
   GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
   GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-  // row = block bits (uniform) | thread bits
-  const int nl = op.n_rows < LB ? op.n_rows : LB;
-  const uint32_t blk = blockIdx.x;
-  const uint32_t oa = dep32_opt(blk, op.row_a, LB, op.n_rows - nl) + dep32_opt(tid, op.row_a, 0, nl);
-  const uint32_t ob = dep32_opt(blk, op.row_b, LB, op.n_rows - nl) + dep32_opt(tid, op.row_b, 0, nl);
-  const uint32_t oc = dep32(blk, op.row_c, LB, op.n_rows - nl) + dep32(tid, op.row_c, 0, nl);
+  const uint32_t r32 = (uint32_t)row;
+  const uint32_t oa = deposit_runs32(r32, op.run_a);
+  const uint32_t ob = deposit_runs32(r32, op.run_b);
+  const uint32_t oc = deposit_runs32(r32, op.run_c);
   uint32_t inb[NIN], inc[NIN];
 #pragma unroll
   for (int j = 0; j < NIN; j++) { inb[j] = dep32(j, op.in_b, 0, op.n_in); inc[j] = dep32(j, op.in_c, 0, op.n_in); }
@@ -173,28 +213,34 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
 #pragma unroll
   for (int j = 0; j < NIN; j++) { acc[j].x = 0; acc[j].y = 0; }
   const uint32_t nk = 1u << op.n_k;
-  if (op.pair_a) {
-    // k and k + 1 are adjacent in A: one 16-byte load for both; the counter
-    // runs over the summed bits above the lowest
-    const uint32_t b1 = 1u << pos_at(op.k_b, 0);
-    uint32_t xa = 0, xb = 0;
-    for (uint32_t k = 0; k < nk; k += 2 * KU) {
-      t4 a2[KU];
-      uint32_t bo[KU];
+  // When no row bit reaches B (a gate or a small tensor applied to every row),
+  // every B address is the same for all threads: B is then read with scalar
+  // loads (once per wavefront) instead of per-lane vector loads.
+  CMEM const V* Bc = reinterpret_cast<CMEM const V*>(reinterpret_cast<uintptr_t>(B));
+  auto walk = [&](auto uniform_b) {
+    constexpr bool UB = decltype(uniform_b)::value;
+    auto ldb = [&](uint32_t off) -> V {
+      if constexpr (UB) return conjv(ldc(Bc + off), op.conj_b);
+      else return conjv(ld(B + off), op.conj_b);
+    };
+    if (op.pair_a) {
+      // k and k + 1 are adjacent in A: one 16-byte load for both; the counter
+      // c runs over the summed bits above the lowest
+      const uint32_t b1 = 1u << pos_at(op.k_b, 0);
+      uint32_t xa = 0, xb = 0, c = 0;
+      for (uint32_t i = 0; i < (nk >> 1); i += U) {
+        t4 a2[U];
+        uint32_t bo[U];
 #pragma unroll
-      for (int u = 0; u < KU; u++)
-        if (k + 2 * u < nk) {
+        for (int u = 0; u < U; u++) {
           a2[u] = *reinterpret_cast<GMEM const t4*>(A + oa + xa);
           bo[u] = ob + xb;
-          const uint32_t c = (k >> 1) + u;      // counter over the summed bits above the lowest
-          if (2 * (c + 1) < nk) {
-            xa += (uint32_t)step_delta(c, op.k_a, 1);
-            xb += (uint32_t)step_delta(c, op.k_b, 1);
-          }
+          xa += (uint32_t)step_delta_n(c, op.k_a, 1, op.n_k - 1);
+          xb += (uint32_t)step_delta_n(c, op.k_b, 1, op.n_k - 1);
+          c++;
         }
 #pragma unroll
-      for (int u = 0; u < KU; u++)
-        if (k + 2 * u < nk) {
+        for (int u = 0; u < U; u++) {
           V a0, a1;
           a0.x = a2[u][0];
           a0.y = op.conj_a ? -a2[u][1] : a2[u][1];
@@ -202,34 +248,34 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
           a1.y = op.conj_a ? -a2[u][3] : a2[u][3];
 #pragma unroll
           for (int j = 0; j < NIN; j++) {
-            acc[j] = cfma(acc[j], a0, conjv(ld(B + bo[u] + inb[j]), op.conj_b));
-            acc[j] = cfma(acc[j], a1, conjv(ld(B + bo[u] + b1 + inb[j]), op.conj_b));
+            acc[j] = cfma(acc[j], a0, ldb(bo[u] + inb[j]));
+            acc[j] = cfma(acc[j], a1, ldb(bo[u] + b1 + inb[j]));
           }
         }
-    }
-  } else {
-    uint32_t xa = 0, xb = 0;
-    for (uint32_t k = 0; k < nk; k += KU) {
-      V a[KU];
-      uint32_t bo[KU];
+      }
+    } else {
+      uint32_t xa = 0, xb = 0, c = 0;
+      for (uint32_t i = 0; i < nk; i += U) {
+        V a[U];
+        uint32_t bo[U];
 #pragma unroll
-      for (int u = 0; u < KU; u++)
-        if (k + u < nk) {
+        for (int u = 0; u < U; u++) {
           a[u] = conjv(ld(A + oa + xa), op.conj_a);
           bo[u] = ob + xb;
-          if (k + u + 1 < nk) {
-            xa += (uint32_t)step_delta(k + u, op.k_a, 0);
-            xb += (uint32_t)step_delta(k + u, op.k_b, 0);
-          }
+          xa += (uint32_t)step_delta_n(c, op.k_a, 0, op.n_k);
+          xb += (uint32_t)step_delta_n(c, op.k_b, 0, op.n_k);
+          c++;
         }
 #pragma unroll
-      for (int u = 0; u < KU; u++)
-        if (k + u < nk) {
+        for (int u = 0; u < U; u++) {
 #pragma unroll
-          for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a[u], conjv(ld(B + bo[u] + inb[j]), op.conj_b));
+          for (int j = 0; j < NIN; j++) acc[j] = cfma(acc[j], a[u], ldb(bo[u] + inb[j]));
         }
+      }
     }
-  }
+  };
+  if (op.run_b.n == 0) walk(std::true_type());
+  else walk(std::false_type());
   if (op.accumulate) {
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
@@ -265,30 +311,31 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// One wavefront per (row, chunk of the summed range): lane l takes
+// One wavefront per (chunk of the summed range, row): lane l takes
 // k = chunk * 2^cbits + 64 t + l for t = 0, 1, ..., so every load of the
 // wavefront covers 64 consecutive k; the lane bits of the offset are fixed
 // and the bits above advance as a masked counter.  Partial sums of the lanes
 // are combined by a fixed butterfly.
-template <typename T, int NIN>
+template <typename T, int NIN, int U>
 __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) {
   using V = typename C2<T>::t;
-  constexpr int KU = NIN <= 2 ? 8 : (NIN <= 4 ? 4 : 2);
   const int z = blockIdx.y;
   const int64_t sid = slice_id(ctx, z);
   if (sid < 0) return;
   const int lane = threadIdx.x & 63;
   const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
-  const uint32_t row = (uint32_t)(wave >> ks);
-  const uint32_t chunk = (uint32_t)(wave & ((uint64_t(1) << ks) - 1));
-  if ((wave >> ks) >> op.n_rows) return;
+  // chunk-major order: the rows of one K chunk are adjacent wavefronts, so the
+  // B values they share are read from HBM once and then hit in L2
+  const uint32_t row = (uint32_t)(wave & ((uint64_t(1) << op.n_rows) - 1));
+  const uint32_t chunk = (uint32_t)(wave >> op.n_rows);
+  if (uint64_t(chunk) >> ks) return;
   const int eb = sizeof(V);
   GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
   GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
   const int cbits = op.n_k - ks;                  // >= 6
-  const uint32_t ba = dep32_opt(row, op.row_a, 0, op.n_rows) + dep32(chunk, op.k_a, cbits, ks) + dep32(lane, op.k_a, 0, 6);
-  const uint32_t bb = dep32_opt(row, op.row_b, 0, op.n_rows) + dep32(chunk, op.k_b, cbits, ks) + dep32(lane, op.k_b, 0, 6);
+  const uint32_t ba = deposit_runs32(row, op.run_a) + dep32(chunk, op.k_a, cbits, ks) + dep32(lane, op.k_a, 0, 6);
+  const uint32_t bb = deposit_runs32(row, op.run_b) + dep32(chunk, op.k_b, cbits, ks) + dep32(lane, op.k_b, 0, 6);
   uint32_t inb[NIN];
 #pragma unroll
   for (int j = 0; j < NIN; j++) inb[j] = dep32(j, op.in_b, 0, op.n_in);
@@ -296,37 +343,34 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
 #pragma unroll
   for (int j = 0; j < NIN; j++) { ar[j] = 0; ai[j] = 0; }
   const uint32_t steps = 1u << (cbits - 6);
-  uint32_t xa = 0, xb = 0;
-  for (uint32_t t = 0; t < steps; t += KU) {
-    V a[KU];
-    uint32_t bo[KU];
+  uint32_t xa = 0, xb = 0, c = 0;
+  for (uint32_t i = 0; i < steps; i += U) {
+    V a[U];
+    uint32_t bo[U];
 #pragma unroll
-    for (int u = 0; u < KU; u++)
-      if (t + u < steps) {
-        a[u] = conjv(ld(A + ba + xa), op.conj_a);
-        bo[u] = bb + xb;
-        if (t + u + 1 < steps) {
-          xa += (uint32_t)step_delta(t + u, op.k_a, 6);
-          xb += (uint32_t)step_delta(t + u, op.k_b, 6);
-        }
+    for (int u = 0; u < U; u++) {
+      a[u] = conjv(ld(A + ba + xa), op.conj_a);
+      bo[u] = bb + xb;
+      xa += (uint32_t)step_delta_n(c, op.k_a, 6, cbits - 6);
+      xb += (uint32_t)step_delta_n(c, op.k_b, 6, cbits - 6);
+      c++;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int j = 0; j < NIN; j++) {
+        const V b = conjv(ld(B + bo[u] + inb[j]), op.conj_b);
+        ar[j] += a[u].x * b.x - a[u].y * b.y;
+        ai[j] += a[u].x * b.y + a[u].y * b.x;
       }
-#pragma unroll
-    for (int u = 0; u < KU; u++)
-      if (t + u < steps) {
-#pragma unroll
-        for (int j = 0; j < NIN; j++) {
-          const V b = conjv(ld(B + bo[u] + inb[j]), op.conj_b);
-          ar[j] += a[u].x * b.x - a[u].y * b.y;
-          ai[j] += a[u].x * b.y + a[u].y * b.x;
-        }
-      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < NIN; j++) { ar[j] = wave_sum(ar[j]); ai[j] = wave_sum(ai[j]); }
   if (lane != 0) return;
   if (ks == 0) {
     GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-    const uint32_t oc = dep32(row, op.row_c, 0, op.n_rows);
+    const uint32_t oc = deposit_runs32(row, op.run_c);
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
       const uint32_t c = oc + dep32(j, op.in_c, 0, op.n_in);
@@ -337,42 +381,49 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
       st(Cp + c, o);
     }
   } else {
+    // partials [row][in][chunk]: the chunks of one output are contiguous
     GMEM V* P = reinterpret_cast<GMEM V*>(resolve(ctx, op.part, z, sid, eb));
-    const uint64_t base = ((uint64_t(chunk) << op.n_rows) + row) * NIN;
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
       V o;
       o.x = ar[j];
       o.y = ai[j];
-      st(P + base + j, o);
+      st(P + ((uint64_t(row) * NIN + j) << ks) + chunk, o);
     }
   }
 }
 
+// Sum of the split-K partials of each output in a fixed order: one wavefront
+// per output, lane l adds chunks l, l + 64, ... (contiguous in the partials
+// buffer), then the fixed butterfly of wave_sum.  Deterministic.
 template <typename T>
 __global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) {
   using V = typename C2<T>::t;
   const int z = blockIdx.y;
   const int64_t sid = slice_id(ctx, z);
   if (sid < 0) return;
-  const int nin = 1 << op.n_in;
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const uint64_t row = t / nin;
-  const int j = (int)(t % nin);
-  if (row >> op.n_rows) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t o = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (o >> (op.n_rows + op.n_in)) return;
   const int eb = sizeof(V);
-  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, eb));
-  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
-  V s;
-  s.x = 0;
-  s.y = 0;
-  const uint64_t nch = uint64_t(1) << op.k_split_bits;
-  for (uint64_t ch = 0; ch < nch; ch++) {
-    const V p = ld(P + ((ch << op.n_rows) + row) * nin + j);
-    s.x += p.x;
-    s.y += p.y;
+  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, eb)) + (o << op.k_split_bits);
+  const uint32_t nch = 1u << op.k_split_bits;
+  T sx = 0, sy = 0;
+  for (uint32_t ch = lane; ch < nch; ch += 64) {
+    const V p = ld(P + ch);
+    sx += p.x;
+    sy += p.y;
   }
-  const uint64_t c = deposit(row, op.row_c, 0, op.n_rows) + deposit(j, op.in_c, 0, op.n_in);
-  if (op.accumulate) { V p = ld(Cp + c); s.x += p.x; s.y += p.y; }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if (lane != 0) return;
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
+  const uint64_t row = o >> op.n_in;
+  const uint32_t j = (uint32_t)(o & ((1u << op.n_in) - 1));
+  const uint64_t c = deposit_runs(row, op.run_c) + deposit(j, op.in_c, 0, op.n_in);
+  V s;
+  s.x = sx;
+  s.y = sy;
+  if (op.accumulate) { V q = ld(Cp + c); s.x += q.x; s.y += q.y; }
   st(Cp + c, s);
 }

@@ -44,6 +44,15 @@ struct Ctx {
   int32_t elem_bytes;     // 8 (complex64) or 16 (complex128)
 };
 
+// A position list as runs: bits src .. src+len-1 of an index land at
+// positions dst .. dst+len-1 of an operand (absent bits are left out).  Kernels
+// deposit an index with one shift-and-mask per run instead of one step per
+// bit; layouts keep consecutive bits together, so there are few runs.
+struct BitRuns {
+  int32_t n;
+  uint32_t r[kMaxBits];   // src | dst << 8 | len << 16
+};
+
 // Row kernel: out[c] = sum_k A[a] * opB(B[b]).  Threads enumerate `rows`
 // (row index bit i has position row_c[i] in C, row_a[i] in A, row_b[i] in B;
 // -1 = absent); each thread computes all 2^n_in outputs of its in-thread bits
@@ -63,6 +72,7 @@ struct RowOp {
   int8_t row_c[kMaxBits], row_a[kMaxBits], row_b[kMaxBits];
   int8_t in_c[kMaxInThread], in_b[kMaxInThread];
   int8_t k_a[kMaxBits], k_b[kMaxBits];
+  BitRuns run_a, run_b, run_c;   // row_a / row_b / row_c as runs
 };
 
 // Matrix-core / tiled GEMM: C[h, m, n] = sum_k A[h, m, k] * opB(B[h, k, n]).
@@ -79,6 +89,8 @@ struct GemmOp {
   int8_t a_m[kMaxBits], c_m[kMaxBits];
   int8_t b_n[kMaxBits], c_n[kMaxBits];
   int8_t a_k[kMaxBits], b_k[kMaxBits];
+  BitRuns run_a_h, run_b_h, run_c_h;     // a_h / b_h / c_h as runs
+  BitRuns run_a_m, run_c_m, run_b_n, run_c_n;
 };
 
 // Fixed-order FP64 accumulation of each in-flight slice's root into dst.
@@ -98,7 +110,21 @@ struct PermuteOp {
   int32_t accumulate;
   int32_t per_slice_serial;// accumulate the in-flight slices one after another (deterministic)
   int8_t src_pos[kMaxBits], dst_pos[kMaxBits];
+  BitRuns run_src, run_dst;      // src_pos / dst_pos as runs
 };
+
+// Runs of a position list (host side; positions < 0 are skipped).
+inline void make_runs(const int8_t* pos, int n, BitRuns& R) {
+  R.n = 0;
+  int i = 0;
+  while (i < n) {
+    if (pos[i] < 0) { i++; continue; }
+    int len = 1;
+    while (i + len < n && pos[i + len] == pos[i] + len) len++;
+    R.r[R.n++] = uint32_t(i) | uint32_t(pos[i]) << 8 | uint32_t(len) << 16;
+    i += len;
+  }
+}
 
 // Device code reads the int8 position lists a dword at a time: every op
 // struct must be 4-byte aligned with a size that is a multiple of 4.

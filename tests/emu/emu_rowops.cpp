@@ -18,6 +18,7 @@
 #include <complex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "plan.h"
@@ -50,6 +51,39 @@ namespace tn {
 }
 using namespace tn;
 
+// Steps per batch of loads, as the library's launcher picks them.
+static int chunk_bits(const RowOp& op) {
+  const int nin = 1 << op.n_in;
+  const int kb = row_ku(nin) == 8 ? 3 : (row_ku(nin) == 4 ? 2 : 1);
+  int ub;
+  if (op.k_split_bits >= 0) ub = op.n_k - (op.k_split_bits > 0 ? op.k_split_bits : 0) - 6;
+  else ub = op.pair_a ? op.n_k - 1 : op.n_k;
+  return ub < kb ? ub : kb;
+}
+
+template <typename T, int NIN>
+static void call_lane(bool splitk, int ub, const Ctx& ctx, const RowOp& op) {
+  constexpr int KU = row_ku(NIN);
+  switch (ub) {
+    case 0: if (splitk) splitk_kernel<T, NIN, 1>(ctx, op); else row_kernel<T, NIN, 1>(ctx, op); break;
+    case 1: if (splitk) splitk_kernel<T, NIN, 2>(ctx, op); else row_kernel<T, NIN, 2>(ctx, op); break;
+    case 2: if constexpr (KU >= 4) { if (splitk) splitk_kernel<T, NIN, 4>(ctx, op); else row_kernel<T, NIN, 4>(ctx, op); } break;
+    default: if constexpr (KU >= 8) { if (splitk) splitk_kernel<T, NIN, 8>(ctx, op); else row_kernel<T, NIN, 8>(ctx, op); } break;
+  }
+}
+
+template <typename T>
+static void call_any(bool splitk, const Ctx& ctx, const RowOp& op) {
+  const int ub = chunk_bits(op);
+  switch (op.n_in) {
+    case 0: call_lane<T, 1>(splitk, ub, ctx, op); break;
+    case 1: call_lane<T, 2>(splitk, ub, ctx, op); break;
+    case 2: call_lane<T, 4>(splitk, ub, ctx, op); break;
+    case 3: call_lane<T, 8>(splitk, ub, ctx, op); break;
+    default: call_lane<T, 16>(splitk, ub, ctx, op); break;
+  }
+}
+
 template <typename T>
 static void run_row(const Ctx& ctx, const RowOp& op, int z) {
   const uint64_t rows = 1ull << op.n_rows;
@@ -59,13 +93,7 @@ static void run_row(const Ctx& ctx, const RowOp& op, int z) {
       blockDim = {(unsigned)kRowThreads, 1, 1};
       blockIdx = {b, (unsigned)z, 0};
       threadIdx = {t, 0, 0};
-      switch (op.n_in) {
-        case 0: row_kernel<T, 1>(ctx, op); break;
-        case 1: row_kernel<T, 2>(ctx, op); break;
-        case 2: row_kernel<T, 4>(ctx, op); break;
-        case 3: row_kernel<T, 8>(ctx, op); break;
-        default: row_kernel<T, 16>(ctx, op); break;
-      }
+      call_any<T>(false, ctx, op);
     }
 }
 
@@ -83,13 +111,7 @@ static void run_splitk(const Ctx& ctx, const RowOp& op, int64_t waves, int z) {
         blockDim = {(unsigned)kRowThreads, 1, 1};
         blockIdx = {(unsigned)(w / wpb), (unsigned)z, 0};
         threadIdx = {(unsigned)((w % wpb) * 64 + l), 0, 0};
-        switch (op.n_in) {
-          case 0: splitk_kernel<T, 1>(ctx, op); break;
-          case 1: splitk_kernel<T, 2>(ctx, op); break;
-          case 2: splitk_kernel<T, 4>(ctx, op); break;
-          case 3: splitk_kernel<T, 8>(ctx, op); break;
-          default: splitk_kernel<T, 16>(ctx, op); break;
-        }
+        call_any<T>(true, ctx, op);
         bar.arrive_and_wait();
       }
     });
@@ -98,15 +120,22 @@ static void run_splitk(const Ctx& ctx, const RowOp& op, int64_t waves, int z) {
 
 template <typename T>
 static void run_reduce(const Ctx& ctx, const RowOp& op, int z) {
-  const uint64_t n = 1ull << (op.n_rows + op.n_in);
-  const unsigned nblk = (unsigned)((n + kRowThreads - 1) / kRowThreads);
-  for (unsigned b = 0; b < nblk; b++)
-    for (unsigned t = 0; t < (unsigned)kRowThreads; t++) {
-      blockDim = {(unsigned)kRowThreads, 1, 1};
-      blockIdx = {b, (unsigned)z, 0};
-      threadIdx = {t, 0, 0};
-      reduce_kernel<T>(ctx, op);
-    }
+  const int64_t waves = int64_t(1) << (op.n_rows + op.n_in);
+  const int wpb = kRowThreads / 64;
+  std::barrier<> bar(64);
+  g_wave_barrier = &bar;
+  std::vector<std::thread> lanes;
+  for (int l = 0; l < 64; l++)
+    lanes.emplace_back([&, l] {
+      for (int64_t w = 0; w < waves; w++) {
+        blockDim = {(unsigned)kRowThreads, 1, 1};
+        blockIdx = {(unsigned)(w / wpb), (unsigned)z, 0};
+        threadIdx = {(unsigned)((w % wpb) * 64 + l), 0, 0};
+        reduce_kernel<T>(ctx, op);
+        bar.arrive_and_wait();
+      }
+    });
+  for (auto& t : lanes) t.join();
 }
 
 int main(int argc, char** argv) {
@@ -188,12 +217,16 @@ int main(int argc, char** argv) {
     *reinterpret_cast<int64_t*>(base + p->counter_off) = 0;
     *reinterpret_cast<int64_t*>(base + p->sid_off) = sid;
     for (const Op& op : p->fwd) {
+      RowOp r = op.row;                       // run tables, as the library's launchers fill them
+      make_runs(r.row_a, r.n_rows, r.run_a);
+      make_runs(r.row_b, r.n_rows, r.run_b);
+      make_runs(r.row_c, r.n_rows, r.run_c);
       if (op.kind == OpKind::RowReduce) {
-        if (eb == 8) run_reduce<float>(ctx, op.row, 0); else run_reduce<double>(ctx, op.row, 0);
-      } else if (op.row.k_split_bits >= 0) {
-        if (eb == 8) run_splitk<float>(ctx, op.row, op.grid_rows, 0); else run_splitk<double>(ctx, op.row, op.grid_rows, 0);
+        if (eb == 8) run_reduce<float>(ctx, r, 0); else run_reduce<double>(ctx, r, 0);
+      } else if (r.k_split_bits >= 0) {
+        if (eb == 8) run_splitk<float>(ctx, r, op.grid_rows, 0); else run_splitk<double>(ctx, r, op.grid_rows, 0);
       } else {
-        if (eb == 8) run_row<float>(ctx, op.row, 0); else run_row<double>(ctx, op.row, 0);
+        if (eb == 8) run_row<float>(ctx, r, 0); else run_row<double>(ctx, r, 0);
       }
     }
     const char* root = base + p->arena_off + p->root_off;

@@ -52,6 +52,17 @@ def test_cfg5_full_slice(oracle_lib, prec):
         assert err / kappa < TOL_C64
 
 
+def test_cfg5h_full_slice(oracle_lib):
+    """The hyperedge variant of cfg5 (fSim as SWAP . diag): batched GEMMs at
+    full size."""
+    err, net, tree, ext, sid = _run("cfg5h", "c64_4m", 33.0, 11, 3, oracle_lib)
+    note("cfg5h rel err", err)
+    if err > TOL_C64:
+        kappa = oracle_lib.root_condition(net, tree, ext, slice_ids=[sid])
+        note("cfg5h kappa", kappa, "backward", err / kappa)
+        assert err / kappa < TOL_C64
+
+
 def test_cfg3_full_slice(oracle_lib):
     err, net, tree, ext, sid = _run("cfg3", "c64_4m", 31.0, 3, 2, oracle_lib)
     note("cfg3 rel err", err)

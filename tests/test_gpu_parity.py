@@ -63,6 +63,21 @@ def test_cfg1_amplitudes_c128(oracle_lib):
         assert abs(complex(got) - complex(ref)) <= TOL_C128 * abs(complex(ref))
 
 
+@pytest.mark.parametrize("prec", ["c64_4m", "c128", "c64_bf16x3", "c64_3m"])
+def test_swap_diag_circuit_sliced(oracle_lib, prec):
+    """fSim as SWAP . diag: wires become hyperedges and most contractions get
+    batch indices (H), matrix-core GEMMs included; 4x5 grid, 12 cycles, three
+    open qubits, sliced to width 16, all slices summed."""
+    net = circuit_network(4, 5, 12, 5, 0b1011001110100101, open_qubits=(2, 9, 13), decompose="swap_diag")
+    tree = find_tree(net, seed=0, trials=4, slice_width=16)
+    sl = list(tree.meta["sliced"])
+    ref = oracle_lib.contract(net, tree, sliced=sl)
+    note("swap_diag", prec, "W", tree.meta["W"], "sliced", sl)
+    got = gpu_sliced(net, tree, sliced=sl, precision=prec)
+    assert got.shape == ref.shape
+    assert rel(got, ref) < TOLS[prec]
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_cfg2_rrg(oracle_lib, seed):
     """120-vertex random 3-regular network: complex128 within 1e-10;

@@ -96,6 +96,26 @@ def test_norm_over_open_outputs(oracle_lib):
     assert rel(psi, sv.run(R * C, net.meta["gates"])) < 1e-12
 
 
+def test_swap_diag_hyperedge_circuit_matches_statevector(oracle_lib):
+    """fSim written as SWAP . diag (hyperedge wires, rank-2 diagonal leaves):
+    the network changes, the amplitudes do not."""
+    R, C, m, seed = 3, 4, 6, 3
+    N = R * C
+    opens = (1, 5, 6, 10)
+    b = 0b011101100110
+    net = circuit_network(R, C, m, seed, b, open_qubits=opens, decompose="swap_diag")
+    assert any(len(set(t)) == 2 and net.leaves[v].shape == (2, 2) for v, t in enumerate(net.leaf_idx))
+    deg = {}
+    for t in net.leaf_idx:
+        for e in t:
+            deg[e] = deg.get(e, 0) + 1
+    assert max(deg.values()) == 3            # wires are hyperedges
+    tree = find_tree(net, seed=1, trials=2)
+    got = oracle_lib.contract(net, tree)
+    ref = sv.amplitude(N, net.meta["gates"], b, open_qubits=opens)
+    assert rel(got, ref) < 1e-12
+
+
 # ---------------------------------------------------------------- brute force
 
 

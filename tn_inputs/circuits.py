@@ -19,8 +19,15 @@ Conventions (the paper fixes only the gate families, not these details):
     index is an open output index, in ascending q order (Sec. 4.7.3: N_f
     output indices left open).
 
-No gate decomposition and no simplification is applied, so every fSim stays a
-rank-4 leaf, as in the Sycamore-53 rows of the benchmark table.
+By default no gate decomposition and no simplification is applied, so every
+fSim stays a rank-4 leaf, as in the Sycamore-53 rows of the benchmark table.
+With decompose="swap_diag" every fSim(pi/2, phi) is written exactly as a SWAP
+after the diagonal gate diag(1, -i, -i, e^{-i phi}) (Sec. 3.5 / 4.6.2: gates
+that are diagonal in the computational basis act on hyperedges): its leaf is
+the rank-2 tensor D[x_a, x_b] on the two incoming wire indices, which then
+continue on the swapped qubits.  Wire indices become hyperedges (the gate that
+produced the wire, the diagonal tensor, the next gate), as in the paper's
+hyperedge rows of the benchmark table.
 """
 
 from __future__ import annotations
@@ -93,9 +100,19 @@ def bit_of(b: int, q: int, N: int) -> int:
     return (b >> (N - 1 - q)) & 1
 
 
+def swap_diag_factor(u: np.ndarray):
+    """(d, ok): U = SWAP . diag(d) for a 4x4 U (basis |00>,|01>,|10>,|11>)?"""
+    swap = np.eye(4, dtype=np.complex128)[[0, 2, 1, 3]]
+    d = np.diag(swap @ u).copy()
+    return d, bool(np.allclose(swap @ np.diag(d), u, atol=1e-14))
+
+
 def circuit_network(R: int, C: int, m: int, seed: int, bitstring: int,
-                    open_qubits=()) -> Network:
-    """Network for <b| U |0^N> with `open_qubits` left open (ascending q)."""
+                    open_qubits=(), decompose: str = "none") -> Network:
+    """Network for <b| U |0^N> with `open_qubits` left open (ascending q);
+    decompose in {"none", "swap_diag"} (see the module docstring)."""
+    if decompose not in ("none", "swap_diag"):
+        raise ValueError(f"unknown decomposition {decompose!r}")
     N = R * C
     gates = random_circuit(R, C, m, seed)
     open_set = set(open_qubits)
@@ -118,6 +135,15 @@ def circuit_network(R: int, C: int, m: int, seed: int, bitstring: int,
             leaf_idx.append([o, wire[q]])
             kinds.append("1q")
             wire[q] = o
+        elif decompose == "swap_diag":
+            qa, qb = qs
+            d, ok = swap_diag_factor(u)
+            if not ok:
+                raise ValueError("two-qubit gate is not SWAP times a diagonal gate")
+            leaves.append(d.reshape(2, 2).copy())          # D[x_a, x_b] = d[2 x_a + x_b]
+            leaf_idx.append([wire[qa], wire[qb]])
+            kinds.append("2q")
+            wire[qa], wire[qb] = wire[qb], wire[qa]
         else:
             qa, qb = qs
             oa, ob = n_idx, n_idx + 1
@@ -137,7 +163,8 @@ def circuit_network(R: int, C: int, m: int, seed: int, bitstring: int,
     out_idx = [wire[q] for q in sorted(open_set)]
     net = Network(leaves, leaf_idx, [2] * n_idx, out_idx,
                   meta=dict(kind="circuit", R=R, C=C, m=m, seed=seed, bitstring=bitstring,
-                            open_qubits=tuple(sorted(open_set)), leaf_kinds=kinds, gates=gates))
+                            open_qubits=tuple(sorted(open_set)), leaf_kinds=kinds, gates=gates,
+                            decompose=decompose))
     net.check()
     return net
 

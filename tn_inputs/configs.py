@@ -10,6 +10,9 @@
   cfg5  6x9 grid circuit, 12 cycles, six open qubits (central 2x3 block, 64
         correlated amplitudes); sliced to width 30; a seeded subset of 256
         slice ids (all ids when there are at most 256)
+  cfg5h the cfg5 circuit with every fSim written as SWAP times a diagonal
+        gate (circuits.circuit_network decompose="swap_diag"): a hyperedge
+        network (batch indices in the contractions); sliced to width 30
 
 They stand in for the paper's GRCS / Sycamore circuit files and random-graph
 instances, which are not available here: same gate families, sizes and
@@ -41,6 +44,8 @@ SPECS = {
     "cfg3": dict(kind="circuit", R=7, C=7, m=14, open=(), trials=24, slice_width=27),
     "cfg4": dict(kind="circuit", R=6, C=6, m=12, open=(), trials=24, slice_width=28),
     "cfg5": dict(kind="circuit", R=6, C=9, m=12, open=CFG5_OPEN, trials=24, slice_width=30),
+    "cfg5h": dict(kind="circuit", R=6, C=9, m=12, open=CFG5_OPEN, trials=24, slice_width=30,
+                  decompose="swap_diag"),
 }
 
 
@@ -51,7 +56,8 @@ def network(name: str, seed: int = 0, bitstring: int | None = None):
     N = s["R"] * s["C"]
     if bitstring is None:
         bitstring = int(np.random.default_rng(seed).integers(0, 2 ** N, dtype=np.uint64)) if N < 64 else 0
-    return circuit_network(s["R"], s["C"], s["m"], seed, bitstring, open_qubits=s["open"])
+    return circuit_network(s["R"], s["C"], s["m"], seed, bitstring, open_qubits=s["open"],
+                           decompose=s.get("decompose", "none"))
 
 
 def _path(name, seed):
@@ -85,9 +91,9 @@ def slice_subset(d_sliced: int, seed: int = 0, size: int = 256):
     return sorted(int(x) for x in ids)
 
 
-def write_all(seeds=(0,)):
+def write_all(seeds=(0,), names=None):
     os.makedirs(TREES, exist_ok=True)
-    for name in SPECS:
+    for name in (names or SPECS):
         for seed in (seeds if name != "cfg2" else range(10)):
             tree = search_tree(name, seed)
             meta = {k: (float(v) if isinstance(v, (float, np.floating)) else v)
@@ -100,4 +106,5 @@ def write_all(seeds=(0,)):
 
 
 if __name__ == "__main__":
-    write_all()
+    import sys
+    write_all(names=sys.argv[1:] or None)
