@@ -343,18 +343,30 @@ def node_bench(spec, precision, reps):
     ws = plan.workspace()
     leaves = [torch.from_numpy(np.ascontiguousarray(t)).to("cuda", plan.storage_dtype) for t in net.leaves]
     out = torch.empty(plan.out_shape, dtype=torch.complex128, device="cuda")
-    plan.tune(ws)
-    plan.contract_sliced_timed(leaves, out=out, workspace=ws)
-    best = None
-    for _ in range(reps):
-        _, ops = plan.contract_sliced_timed(leaves, out=out, workspace=ws)
-        op = max(ops, key=lambda o: o["ms"])
-        best = op if best is None or op["ms"] < best["ms"] else best
     node = plan.nodes()[0]
+    # the operands are leaves, which tn_plan_tune does not time: every tile
+    # variant that applies is timed here instead
+    per_tile = {}
+    best = None
+    for t in (range(10) if node["kclass"] == "gemm" else [0]):
+        if t == 4 or (t and plan.set_tile(t) == 0 and t != 0):
+            continue
+        if t == 0:
+            plan.set_tile(0)
+        plan.contract_sliced_timed(leaves, out=out, workspace=ws)
+        tbest = None
+        for _ in range(reps):
+            _, ops = plan.contract_sliced_timed(leaves, out=out, workspace=ws)
+            op = max(ops, key=lambda o: o["ms"])
+            tbest = op if tbest is None or op["ms"] < tbest["ms"] else tbest
+        per_tile[t] = round(tbest["ms"], 4)
+        if best is None or tbest["ms"] < best[1]["ms"]:
+            best = (t, tbest)
+    t, best = best
     print(json.dumps({"mode": "node", "shape_mnk": [m, n, k], "precision": precision, "kernel_class": node["kclass"],
-                      "kernel": best["kind"], "ms": round(best["ms"], 4),
+                      "kernel": best["kind"], "tile": t, "ms": round(best["ms"], 4),
                       "tflops": round(best["flops"] / best["ms"] / 1e9, 2),
-                      "gbs": round(best["bytes"] / best["ms"] / 1e6, 1), "reps": reps}))
+                      "gbs": round(best["bytes"] / best["ms"] / 1e6, 1), "ms_per_tile": per_tile, "reps": reps}))
 
 
 def main():

@@ -141,6 +141,19 @@ int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t*
 int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void* stream);
 
 /*
+ * Pin the tile variant of every matrix-core contraction of the plan (forward
+ * and backward programs) that variant `tile` can run, in place of the default
+ * or autotuned choice; the others keep theirs.  Variants: 0 = 128x128,
+ * 1 = 64x128, 2 = 128x64, 3 = 64x64 (every precision); 4 = vector ALU; for
+ * TN_C64_4M also 5 = 256x128, 6 = 128x128 with raised matrix-core priority,
+ * 7 = 128x128, 8 = 256x128 and 9 = 128x128 at three waves per SIMD, all
+ * direct-to-LDS (operands whose summed indices are their lowest axes).  *n_set (may be NULL) receives the number of
+ * contractions changed.  TN_E_INVALID for an unknown variant.  Used to test
+ * every variant and to reproduce a tuned plan.
+ */
+int tn_plan_set_tile(tn_plan_t plan, int32_t tile, int32_t* n_set);
+
+/*
  * Contract an unsliced plan (n_sliced == 0).
  * leaves[v]   device pointer to leaf v (complex64, or complex128 for TN_C128)
  * out         device pointer, output in the plan's storage type, out_idx order

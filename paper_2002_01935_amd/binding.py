@@ -12,6 +12,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: it carries its own HIP / HSA runtime libraries, and libtn.so must
+# bind to the HIP runtime torch has loaded (one runtime per process); loading
+# libtn.so first would bring in a second HSA runtime that finds no device.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtn.so")
@@ -23,7 +27,7 @@ KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm"}
 EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
-    "tn_last_error", "tn_contract_sliced_timed",
+    "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile",
 ]
 OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
 
@@ -51,6 +55,7 @@ def _load():
     lib.tn_plan_num_nodes.argtypes = [P, P]
     lib.tn_plan_node_info.argtypes = [P, i32, P, P, P, P, P, P, P]
     lib.tn_plan_tune.argtypes = [P, P, u64, P]
+    lib.tn_plan_set_tile.argtypes = [P, i32, P]
     lib.tn_contract.argtypes = [P, P, P, P, u64, P]
     lib.tn_contract_sliced.argtypes = [P, P, i64, P, P, P, u64, P]
     lib.tn_contract_backward.argtypes = [P, P, P, i32, P, P, i64, P, P, u64, P]
@@ -178,6 +183,13 @@ class Plan:
     def tune(self, workspace, stream=None):
         _check(lib.tn_plan_tune(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                 _stream(stream)))
+
+    def set_tile(self, tile) -> int:
+        """Pin matrix-core tile variant `tile` wherever it applies; returns the
+        number of contractions changed (tn_plan_set_tile)."""
+        n = ctypes.c_int32()
+        _check(lib.tn_plan_set_tile(self.handle, int(tile), ctypes.byref(n)))
+        return n.value
 
     def contract(self, leaves, out=None, workspace=None, stream=None):
         torch = self._check_leaves(leaves)

@@ -547,8 +547,7 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     // for the trials (time per tile scales with K, the ranking does not)
     const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
     for (int t = 0; t < kNumGemmTiles; t++) {
-      if (t == kValuTile) continue;
-      if (p->prec != TN_C64_4M && t >= kNumTilesShared) continue;
+      if (t == kValuTile || !gemm_tile_ok(g, t, p->prec)) continue;
       GemmOp trial = g;
       trial.tile = t;
       trial.n_k = std::min(trial.n_k, 9);
@@ -573,6 +572,25 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
   p->graphs.clear();
   p->tuned = true;
+  return TN_OK;
+}
+
+extern "C" int tn_plan_set_tile(tn_plan_t p, int32_t tile, int32_t* n_set) {
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  int bm, bn;
+  if (gemm_tile_bits(tile, &bm, &bn)) return set_err(TN_E_INVALID, "unknown tile variant");
+  int32_t n = 0;
+  for (auto* prog : {&p->fwd, &p->bwd})
+    for (Op& op : *prog)
+      if (op.kind == OpKind::Gemm && op.gemm.tile != tile && gemm_tile_ok(op.gemm, tile, p->prec)) {
+        op.gemm.tile = tile;
+        n++;
+      }
+  if (n) {
+    for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+    p->graphs.clear();
+  }
+  if (n_set) *n_set = n;
   return TN_OK;
 }
 

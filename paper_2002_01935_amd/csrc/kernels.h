@@ -17,7 +17,9 @@ hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s)
 hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s);
 // log2 tile sizes of a gemm tile variant; -1 if unknown
 int gemm_tile_bits(int tile, int* bm, int* bn);
-constexpr int kNumGemmTiles = 7;
+// whether tile variant `tile` can run op at precision prec
+bool gemm_tile_ok(const GemmOp& op, int tile, int prec);
+constexpr int kNumGemmTiles = 10;
 constexpr int kNumTilesShared = 4;   // tiles 0..3 exist for every matrix-core kernel
 constexpr int kValuTile = 4;   // vector-ALU variant (complex128 and reference)
 

@@ -406,6 +406,144 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
+// 4M for operands whose summed bits are their lowest positions, in order
+// (k bit i at position i: every intermediate the planner lays out, and most
+// leaves).  Each tile row is then 8 contiguous complex values per stage, so
+// the stage is copied straight from global memory into LDS by
+// global_load_lds_dwordx4 (16 bytes = two complex values per lane, no
+// registers in between), into a ring of three LDS buffers: two stages are in
+// flight while the matrix cores work on the third, with one barrier per stage.
+// LDS keeps the complex values interleaved, 4 units of 16 bytes per row; the
+// unit holding k pair kp of row r sits at r * 4 + (kp ^ ((r >> 2) & 3)), a
+// swizzle applied by choosing which element each lane loads (the lane's LDS
+// slot is fixed), so that the 128-bit fragment reads of 16 lanes hit disjoint
+// banks.  A lane of half hi reads complex k = 4q + 2hi, 4q + 2hi + 1 of its row
+// as (re, im, re, im); the four matrix-core ops of k group q pair the real k
+// indices (re, im, re, im of 4q + {0, 1}) of the lower half with those of
+// 4q + {2, 3} of the upper half, and each lane forms the matching entries of
+// [[Br Bi] [-Bi Br]] from its B unit with selects.
+template <int BM, int BN, int WGM, int WGN, int OCC = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_4m_dl(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  constexpr int IA = BM * 4 / 64 / NW, IB = BN * 4 / 64 / NW;   // load instructions per wave and stage
+  constexpr int NBUF = 3;
+  constexpr int UNITS = (BM + BN) * 4;                            // 16-byte units per buffer
+  static_assert(FM >= 1 && FN >= 1 && IA >= 1 && IB >= 1, "tile too small");
+  static_assert(IA * NW * 64 == BM * 4 && IB * NW * 64 == BN * 4, "tile / wave mismatch");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) f4 lds[NBUF * UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+                         deposit_runs(g.h, op.run_a_h);
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+                         deposit_runs(g.h, op.run_b_h);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // element offset (tile row, k pair) of every unit this lane loads
+  uint32_t a_off[IA], b_off[IB];          // tensors hold fewer than 2^32 elements
+  {
+    const uint64_t mrows = uint64_t(1) << g.tm, nrows = uint64_t(1) << g.tn;
+#pragma unroll
+    for (int i = 0; i < IA; i++) {
+      const int slot = (wave * IA + i) * 64 + lane;
+      const int r = slot >> 2, kp = (slot & 3) ^ ((r >> 2) & 3);
+      const uint64_t rr = uint64_t(r) < mrows ? uint64_t(r) : 0;      // rows past a partial tile repeat row 0
+      a_off[i] = (uint32_t)deposit_runs((g.tile_m << g.tm) | rr, op.run_a_m) + 2 * kp;
+    }
+#pragma unroll
+    for (int i = 0; i < IB; i++) {
+      const int slot = (wave * IB + i) * 64 + lane;
+      const int r = slot >> 2, kp = (slot & 3) ^ ((r >> 2) & 3);
+      const uint64_t rr = uint64_t(r) < nrows ? uint64_t(r) : 0;
+      b_off[i] = (uint32_t)deposit_runs((g.tile_n << g.tn) | rr, op.run_b_n) + 2 * kp;
+    }
+  }
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - RK);
+  auto issue = [&](uint64_t step) {
+    const int buf = (int)(step % NBUF);
+    const uint32_t k0 = (uint32_t)(step << RK);
+#pragma unroll
+    for (int i = 0; i < IA; i++)
+      __builtin_amdgcn_global_load_lds((GMEM const void*)(A + a_off[i] + k0),
+                                       (__attribute__((address_space(3))) void*)(&lds[buf * UNITS + (wave * IA + i) * 64]),
+                                       16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < IB; i++)
+      __builtin_amdgcn_global_load_lds((GMEM const void*)(B + b_off[i] + k0),
+                                       (__attribute__((address_space(3))) void*)(&lds[buf * UNITS + BM * 4 + (wave * IB + i) * 64]),
+                                       16, 0, 0);
+  };
+
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int hi = lane >> 5, c32 = lane & 31, p = c32 & 1;
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  issue(0);
+  if (nsteps > 1) issue(1);
+  for (uint64_t s = 0; s < nsteps; s++) {
+    // this wave's loads of stage s are done once at most those of stage s + 1
+    // remain (the direct-to-LDS data is in LDS when its load retires)
+    if (s + 1 < nsteps) __builtin_amdgcn_s_waitcnt((IA + IB) | (0x7 << 4) | (0xF << 8));
+    else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
+    // every wave's stage s has landed and every wave is done with the buffer
+    // of stage s - 1 (its fragment reads were consumed by the matrix cores);
+    // a plain barrier: a fence here would also drain the stage s + 1 loads
+    __builtin_amdgcn_s_barrier();
+    if (s + 2 < nsteps) issue(s + 2);
+    const f4* L = &lds[(int)(s % NBUF) * UNITS];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int kp = 2 * q + hi;
+      f4 fa[FM];
+#pragma unroll
+      for (int i = 0; i < FM; i++) {
+        const int r = wm * WM + i * 32 + c32;
+        fa[i] = L[r * 4 + (kp ^ ((r >> 2) & 3))];
+        fa[i][1] *= sa;
+        fa[i][3] *= sa;
+      }
+      // one B fragment at a time (fewer live registers), the next one read
+      // while the matrix cores work on this one; consecutive matrix-core ops
+      // alternate between the FM accumulators of column block j
+      auto bunit = [&](int j) {
+        const int n = wn * WN + j * 16 + (c32 >> 1);
+        return L[BM * 4 + n * 4 + (kp ^ ((n >> 2) & 3))];
+      };
+      f4 u = bunit(0);
+#pragma unroll
+      for (int j = 0; j < FN; j++) {
+        const f4 uj = u;
+        if (j + 1 < FN) u = bunit(j + 1);
+        const float br0 = uj[0], bi0 = sb * uj[1], br1 = uj[2], bi1 = sb * uj[3];
+        f4 v;
+        v[0] = p ? bi0 : br0;       // real k = re of the first complex k
+        v[1] = p ? br0 : -bi0;      // im of the first
+        v[2] = p ? bi1 : br1;       // re of the second
+        v[3] = p ? br1 : -bi1;      // im of the second
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+#pragma unroll
+          for (int i = 0; i < FM; i++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][e], v[e], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();                         // the epilogue reuses the LDS ring for its tables
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
+}
+
 // 3M (Gauss) on FP32 matrix cores: with T1 = Ar Br, T2 = Ai Bi and
 // T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2 and Im = T3 - T1 - T2: three real
 // products per complex product instead of four.  Each v_mfma_f32_32x32x2f32
@@ -913,8 +1051,26 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 4: *bm = 6; *bn = 6; return 0;     // vector-ALU 64 x 64
     case 5: *bm = 8; *bn = 7; return 0;     // 256 x 128, 8 waves (4M only)
     case 6: *bm = 7; *bn = 7; return 0;     // 128 x 128 with raised matrix-core priority (4M only)
+    case 7: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring (4M, summed bits lowest)
+    case 8: *bm = 8; *bn = 7; return 0;     // 256 x 128 direct-to-LDS ring, 8 waves
+    case 9: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring, 3 waves per SIMD
     default: return -1;
   }
+}
+
+bool gemm_tile_ok(const GemmOp& op, int tile, int prec) {
+  int bm, bn;
+  if (gemm_tile_bits(tile, &bm, &bn)) return false;
+  if (prec == TN_C128) return tile == kValuTile;
+  if (tile < kNumTilesShared || tile == kValuTile) return true;
+  if (prec != TN_C64_4M) return false;
+  if (tile >= 7) {
+    // the summed bits must be the lowest positions of both operands, in order
+    if (op.n_k < 3) return false;
+    for (int i = 0; i < op.n_k; i++)
+      if (op.a_k[i] != i || op.b_k[i] != i) return false;
+  }
+  return true;
 }
 
 hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s) {
@@ -929,7 +1085,7 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s
   int bm, bn;
   int tile = op.tile;
   if (prec == TN_C128) tile = 4;
-  if (gemm_tile_bits(tile, &bm, &bn)) return hipErrorInvalidValue;
+  if (gemm_tile_bits(tile, &bm, &bn) || !gemm_tile_ok(op, tile, prec)) return hipErrorInvalidValue;
   const int tm = op.n_m < bm ? op.n_m : bm, tn = op.n_n < bn ? op.n_n : bn;
   const uint64_t tiles = uint64_t(1) << ((op.n_m - tm) + (op.n_n - tn));
   const uint64_t gy = uint64_t(ctx.n_batch) << op.n_h;
@@ -971,6 +1127,9 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s
     case 3: hipLaunchKernelGGL((gemm_mfma_4m<64, 64, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
     case 5: hipLaunchKernelGGL((gemm_mfma_4m<256, 128, 4, 2>), grid, dim3(512), 0, s, ctx, op); break;
     case 6: hipLaunchKernelGGL((gemm_mfma_4m<128, 128, 2, 2, 1>), grid, dim3(256), 0, s, ctx, op); break;
+    case 7: hipLaunchKernelGGL((gemm_mfma_4m_dl<128, 128, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+    case 8: hipLaunchKernelGGL((gemm_mfma_4m_dl<256, 128, 4, 2>), grid, dim3(512), 0, s, ctx, op); break;
+    case 9: hipLaunchKernelGGL((gemm_mfma_4m_dl<128, 128, 2, 2, 3>), grid, dim3(256), 0, s, ctx, op); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -78,6 +78,45 @@ def test_swap_diag_circuit_sliced(oracle_lib, prec):
     assert rel(got, ref) < TOLS[prec]
 
 
+def _canonical_pair(h, m, n, k, seed):
+    """A(H, M, K) x B(H, N, K) with the summed bits lowest in both operands."""
+    H = list(range(h))
+    M = list(range(h, h + m))
+    K = list(range(h + m, h + m + k))
+    N = list(range(h + m + k, h + m + k + n))
+    rng = np.random.default_rng(seed)
+    a = (rng.normal(size=(2,) * (h + m + k)) + 1j * rng.normal(size=(2,) * (h + m + k)))
+    b = (rng.normal(size=(2,) * (h + n + k)) + 1j * rng.normal(size=(2,) * (h + n + k)))
+    return Network([a, b], [H + M + K, H + N + K], [2] * (h + m + n + k), H + M + N)
+
+
+TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3], "c64_bf16x3": [0, 1, 2, 3]}
+
+
+@pytest.mark.parametrize("prec", sorted(TILE_CASES))
+def test_every_tile_variant(oracle_lib, prec):
+    """Each matrix-core tile variant pinned with tn_plan_set_tile, on pairwise
+    nodes with the summed bits lowest (full and partial tiles, batch bits, K of
+    one stage and of many) and on a hyperedge circuit whose intermediates the
+    planner lays out."""
+    nets = [(_canonical_pair(*s, seed=i), TWO, ()) for i, s in
+            enumerate([(0, 8, 9, 5), (2, 7, 6, 3), (0, 10, 10, 8), (1, 5, 9, 12), (0, 9, 8, 4)])]
+    cnet = circuit_network(4, 5, 12, 5, 0b1011001110100101, open_qubits=(2, 9, 13), decompose="swap_diag")
+    ctree = find_tree(cnet, seed=0, trials=4, slice_width=16)
+    nets.append((cnet, ctree, list(ctree.meta["sliced"])))
+    from paper_2002_01935_amd.binding import Plan
+    for ni, (net, tree, sl) in enumerate(nets):
+        ref = oracle_lib.contract(net, tree, sliced=sl)
+        for t in TILE_CASES[prec]:
+            plan = Plan(net, tree, sliced=sl, precision=prec)
+            changed = plan.set_tile(t)
+            if t != 0 and changed == 0:
+                continue
+            note("tile", prec, t, "net", ni, "changed", changed)
+            got = gpu_sliced(net, tree, sliced=sl, precision=prec, plan=plan)
+            assert rel(got, ref) < TOLS[prec], (prec, t, ni)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_cfg2_rrg(oracle_lib, seed):
     """120-vertex random 3-regular network: complex128 within 1e-10;

@@ -117,3 +117,31 @@ def test_backward_plan_recomputes(B):
     nodes = p.nodes()
     assert bi["flops_per_slice"] >= 2.9 * info["flops_per_slice"]
     assert bi["flops_per_slice"] <= 5.0 * info["flops_per_slice"]
+
+
+def _canonical_pair(m, n, k, k_first=False):
+    """A(M, K) x B(N, K), summed bits lowest in both (or highest in A)."""
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(2,) * (m + k)) + 0j
+    b = rng.normal(size=(2,) * (n + k)) + 0j
+    return Network([a, b], [(K + M) if k_first else (M + K), N + K], [2] * (m + n + k), M + N)
+
+
+def test_set_tile(B):
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    net = _canonical_pair(7, 7, 5)
+    p = B.Plan(net, two, precision="c64_4m")
+    assert [n["kclass"] for n in p.nodes()] == ["gemm"]
+    assert p.set_tile(7) == 1          # direct-to-LDS variant applies: summed bits lowest
+    assert p.set_tile(7) == 0          # already set
+    assert p.set_tile(0) == 1
+    p3 = B.Plan(net, two, precision="c64_3m")
+    assert p3.set_tile(7) == 0         # 4M-only variant
+    assert p3.set_tile(1) == 1
+    q = B.Plan(_canonical_pair(7, 7, 5, k_first=True), two, precision="c64_4m")
+    assert q.set_tile(8) == 0          # summed bits not lowest in A
+    assert q.set_tile(5) == 1
+    with pytest.raises(B.TNError) as e:
+        p.set_tile(99)
+    assert e.value.code == -1
