@@ -38,6 +38,9 @@ namespace tn {
 #define GMEM __attribute__((address_space(1)))
 // Constant address space: uniform read-only data, loaded with scalar loads.
 #define CMEM __attribute__((address_space(4)))
+// Point where all lanes of a wavefront have passed the preceding LDS writes
+// (a wavefront runs its lanes together: only compiler reordering is fenced).
+#define TN_WAVE_SYNC() __builtin_amdgcn_wave_barrier()
 
 #include "rowops.h"
 
@@ -978,9 +981,11 @@ template <typename T, int NIN>
 static void launch_row_u(bool splitk, dim3 grid, const Ctx& ctx, const RowOp& op, int ubits, hipStream_t s) {
   constexpr int KB = row_ku(NIN) == 8 ? 3 : (row_ku(NIN) == 4 ? 2 : 1);
   const int ub = ubits < KB ? ubits : KB;
+  const bool stage = !splitk && op.stage_c && sizeof(T) == 4;
 #define TN_ROW_LAUNCH(U)                                                                            \
   do {                                                                                              \
     if (splitk) hipLaunchKernelGGL((splitk_kernel<T, NIN, U>), grid, dim3(kRowThreads), 0, s, ctx, op); \
+    else if (stage) hipLaunchKernelGGL((row_kernel<T, NIN, U, true>), grid, dim3(kRowThreads), 0, s, ctx, op); \
     else hipLaunchKernelGGL((row_kernel<T, NIN, U>), grid, dim3(kRowThreads), 0, s, ctx, op);          \
   } while (0)
   switch (ub) {
@@ -1025,6 +1030,12 @@ static RowOp with_runs(const RowOp& in) {
   make_runs(op.row_a, op.n_rows, op.run_a);
   make_runs(op.row_b, op.n_rows, op.run_b);
   make_runs(op.row_c, op.n_rows, op.run_c);
+  // staged stores: complex64, no accumulation, the in-thread values at C's
+  // lowest positions and the six lane bits of the row right above them
+  bool st = op.k_split_bits < 0 && op.pair_c && !op.accumulate && op.n_in >= 1 && op.n_rows >= 6;
+  for (int i = 0; st && i < op.n_in; i++) st = op.in_c[i] == i;
+  for (int i = 0; st && i < 6; i++) st = op.row_c[i] == op.n_in + i;
+  op.stage_c = st ? 1 : 0;
   return op;
 }
 

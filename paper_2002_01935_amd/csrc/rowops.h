@@ -188,7 +188,7 @@ constexpr int row_ku(int nin) { return nin <= 2 ? 8 : (nin <= 4 ? 4 : 2); }
 // offsets advanced as masked counters, and a batch of A loads (and the B
 // loads that go with them) is issued before any of it is used, so that each
 // thread keeps several memory requests in flight.
-template <typename T, int NIN, int U>
+template <typename T, int NIN, int U, bool STAGE = false>
 __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
   using V = typename C2<T>::t;
   typedef T t4 __attribute__((ext_vector_type(4)));
@@ -284,7 +284,34 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
       acc[j].y += o.y;
     }
   }
-  if (NIN >= 2 && op.pair_c) {
+  if constexpr (STAGE && NIN >= 2) {
+    // The wavefront's output is one contiguous block of 64 * NIN values:
+    // each lane puts its NIN values into the wavefront's LDS area (rows
+    // padded by 16 bytes against bank conflicts) and the wavefront then
+    // stores the block in 1 KiB pieces (16 bytes per lane), instead of
+    // 16-byte pieces at a row stride that touch 64 cache lines per store.
+    constexpr int RS = NIN * 8 + 16;                        // bytes per staged row
+    __shared__ __attribute__((aligned(16))) char stage[kRowThreads / 64][64 * RS];
+    const int lane = tid & 63;
+    char* S = &stage[tid >> 6][0];
+#pragma unroll
+    for (int j = 0; j < NIN; j += 2) {
+      t4 w;
+      w[0] = acc[j].x;
+      w[1] = acc[j].y;
+      w[2] = acc[j + 1].x;
+      w[3] = acc[j + 1].y;
+      *reinterpret_cast<t4*>(S + lane * RS + j * 8) = w;
+    }
+    // one wavefront's area only: its LDS accesses are performed in order
+    TN_WAVE_SYNC();
+    GMEM t4* D = reinterpret_cast<GMEM t4*>(Cp + deposit_runs32(r32 & ~63u, op.run_c));
+#pragma unroll
+    for (int t = 0; t < NIN / 2; t++) {
+      const int c = lane + 64 * t;                           // 16-byte piece of the block
+      D[c] = *reinterpret_cast<const t4*>(S + (c / (NIN / 2)) * RS + (c % (NIN / 2)) * 16);
+    }
+  } else if (NIN >= 2 && op.pair_c) {
     // in-thread values j and j + 1 are adjacent in C
 #pragma unroll
     for (int j = 0; j < NIN; j += 2) {

@@ -69,6 +69,7 @@ struct RowOp {
   int32_t accumulate;      // add into C instead of overwriting
   int32_t pair_a;          // A's lowest summed bit sits at position 0 and A's base is pair-aligned: 16-byte loads over k
   int32_t pair_c;          // C's lowest in-thread bit sits at position 0: 16-byte stores over the in-thread values
+  int32_t stage_c;         // a wavefront's 64 rows x in-thread values are one contiguous block of C (set at launch)
   int8_t row_c[kMaxBits], row_a[kMaxBits], row_b[kMaxBits];
   int8_t in_c[kMaxInThread], in_b[kMaxInThread];
   int8_t k_a[kMaxBits], k_b[kMaxBits];

@@ -32,9 +32,12 @@ static thread_local Dim3 threadIdx, blockIdx, blockDim;
 #define __forceinline__ inline
 #define __launch_bounds__(x)
 #define GMEM
+#define __shared__ static
 #define CMEM
 
 static std::barrier<>* g_wave_barrier = nullptr;
+// lanes of a wavefront run as host threads in lockstep at this point
+#define TN_WAVE_SYNC() g_wave_barrier->arrive_and_wait()
 static double g_lane_value[64];
 template <typename T>
 static T __shfl_xor(T v, int mask, int) {
@@ -61,26 +64,40 @@ static int chunk_bits(const RowOp& op) {
   return ub < kb ? ub : kb;
 }
 
+// the library's launcher picks the staged-store variant under these conditions
+static bool staged(const RowOp& op, int eb) {
+  bool st = eb == 8 && op.k_split_bits < 0 && op.pair_c && !op.accumulate && op.n_in >= 1 && op.n_rows >= 6;
+  for (int i = 0; st && i < op.n_in; i++) st = op.in_c[i] == i;
+  for (int i = 0; st && i < 6; i++) st = op.row_c[i] == op.n_in + i;
+  return st;
+}
+
+template <typename T, int NIN, int U>
+static void call_row(bool stage, const Ctx& ctx, const RowOp& op) {
+  if (stage) row_kernel<T, NIN, U, true>(ctx, op);
+  else row_kernel<T, NIN, U>(ctx, op);
+}
+
 template <typename T, int NIN>
-static void call_lane(bool splitk, int ub, const Ctx& ctx, const RowOp& op) {
+static void call_lane(bool splitk, int ub, const Ctx& ctx, const RowOp& op, bool stage = false) {
   constexpr int KU = row_ku(NIN);
   switch (ub) {
-    case 0: if (splitk) splitk_kernel<T, NIN, 1>(ctx, op); else row_kernel<T, NIN, 1>(ctx, op); break;
-    case 1: if (splitk) splitk_kernel<T, NIN, 2>(ctx, op); else row_kernel<T, NIN, 2>(ctx, op); break;
-    case 2: if constexpr (KU >= 4) { if (splitk) splitk_kernel<T, NIN, 4>(ctx, op); else row_kernel<T, NIN, 4>(ctx, op); } break;
-    default: if constexpr (KU >= 8) { if (splitk) splitk_kernel<T, NIN, 8>(ctx, op); else row_kernel<T, NIN, 8>(ctx, op); } break;
+    case 0: if (splitk) splitk_kernel<T, NIN, 1>(ctx, op); else call_row<T, NIN, 1>(stage, ctx, op); break;
+    case 1: if (splitk) splitk_kernel<T, NIN, 2>(ctx, op); else call_row<T, NIN, 2>(stage, ctx, op); break;
+    case 2: if constexpr (KU >= 4) { if (splitk) splitk_kernel<T, NIN, 4>(ctx, op); else call_row<T, NIN, 4>(stage, ctx, op); } break;
+    default: if constexpr (KU >= 8) { if (splitk) splitk_kernel<T, NIN, 8>(ctx, op); else call_row<T, NIN, 8>(stage, ctx, op); } break;
   }
 }
 
 template <typename T>
-static void call_any(bool splitk, const Ctx& ctx, const RowOp& op) {
+static void call_any(bool splitk, const Ctx& ctx, const RowOp& op, bool stage = false) {
   const int ub = chunk_bits(op);
   switch (op.n_in) {
-    case 0: call_lane<T, 1>(splitk, ub, ctx, op); break;
-    case 1: call_lane<T, 2>(splitk, ub, ctx, op); break;
-    case 2: call_lane<T, 4>(splitk, ub, ctx, op); break;
-    case 3: call_lane<T, 8>(splitk, ub, ctx, op); break;
-    default: call_lane<T, 16>(splitk, ub, ctx, op); break;
+    case 0: call_lane<T, 1>(splitk, ub, ctx, op, stage); break;
+    case 1: call_lane<T, 2>(splitk, ub, ctx, op, stage); break;
+    case 2: call_lane<T, 4>(splitk, ub, ctx, op, stage); break;
+    case 3: call_lane<T, 8>(splitk, ub, ctx, op, stage); break;
+    default: call_lane<T, 16>(splitk, ub, ctx, op, stage); break;
   }
 }
 
@@ -88,6 +105,25 @@ template <typename T>
 static void run_row(const Ctx& ctx, const RowOp& op, int z) {
   const uint64_t rows = 1ull << op.n_rows;
   const unsigned nblk = (unsigned)((rows + kRowThreads - 1) / kRowThreads);
+  if (staged(op, sizeof(T) * 2)) {
+    // lanes exchange values through LDS: run each wavefront's lanes together
+    const int64_t waves = (int64_t)nblk * (kRowThreads / 64);
+    std::barrier<> bar(64);
+    g_wave_barrier = &bar;
+    std::vector<std::thread> lanes;
+    for (int l = 0; l < 64; l++)
+      lanes.emplace_back([&, l] {
+        for (int64_t w = 0; w < waves; w++) {
+          blockDim = {(unsigned)kRowThreads, 1, 1};
+          blockIdx = {(unsigned)(w / (kRowThreads / 64)), (unsigned)z, 0};
+          threadIdx = {(unsigned)((w % (kRowThreads / 64)) * 64 + l), 0, 0};
+          call_any<T>(false, ctx, op, true);
+          bar.arrive_and_wait();
+        }
+      });
+    for (auto& t : lanes) t.join();
+    return;
+  }
   for (unsigned b = 0; b < nblk; b++)
     for (unsigned t = 0; t < (unsigned)kRowThreads; t++) {
       blockDim = {(unsigned)kRowThreads, 1, 1};

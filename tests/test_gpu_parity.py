@@ -90,6 +90,22 @@ def _canonical_pair(h, m, n, k, seed):
     return Network([a, b], [H + M + K, H + N + K], [2] * (h + m + n + k), H + M + N)
 
 
+@pytest.mark.parametrize("shape", [(12, 1, 2), (14, 2, 1), (10, 3, 0), (11, 4, 2), (6, 2, 3), (9, 4, 5)])
+def test_row_staged_stores(oracle_lib, shape):
+    """Row kernel whose output rows are staged through LDS (the in-thread values
+    lowest in C, the row bits right above them)."""
+    m, n, k = shape
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(sum(shape))
+    a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+    b = rng.normal(size=(2,) * (n + k)) + 1j * rng.normal(size=(2,) * (n + k))
+    net = Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
+    ref = oracle_lib.contract(net, TWO)
+    for prec in ("c64_4m", "c128"):
+        assert rel(gpu_sliced(net, TWO, precision=prec), ref) < TOLS[prec]
+        assert rel(gpu_contract(net, TWO, precision=prec), ref) < TOLS[prec]
+
+
 TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3], "c64_bf16x3": [0, 1, 2, 3]}
 
 

@@ -82,6 +82,27 @@ def test_pairwise_emulated(emu, oracle_lib, tmp_path, shape, prec):
         assert rel(got, ref) < TOL[prec], (shape, prec, seed)
 
 
+def _canonical_rows(m, n, k, seed):
+    """A(M, K) x B(N, K) -> C(M, N) with C's free-right bits lowest and the
+    row bits right above them (the row kernel's staged-store layout)."""
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+    b = rng.normal(size=(2,) * (n + k)) + 1j * rng.normal(size=(2,) * (n + k))
+    from tn_inputs.network import Network
+    return Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
+
+
+@pytest.mark.parametrize("shape", [(9, 1, 2), (10, 2, 1), (8, 3, 0), (8, 4, 2), (6, 2, 3)])
+def test_staged_rows_emulated(emu, oracle_lib, tmp_path, shape):
+    """Row kernel with the output transposed through LDS (64 rows of a
+    wavefront stored as one block)."""
+    net = _canonical_rows(*shape, seed=sum(shape))
+    got = run(emu, net, "c64_4m", tmp=str(tmp_path))
+    assert got is not None
+    assert rel(got, oracle_lib.contract(net, TWO).ravel()) < TOL["c64_4m"]
+
+
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])
 def test_sliced_emulated(emu, oracle_lib, tmp_path, prec):
     """Slices fixed by the per-leaf slice offsets: the sum of the per-slice
