@@ -145,10 +145,11 @@ int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void
  * and backward programs) that variant `tile` can run, in place of the default
  * or autotuned choice; the others keep theirs.  Variants: 0 = 128x128,
  * 1 = 64x128, 2 = 128x64, 3 = 64x64 (every precision); 4 = vector ALU; for
- * TN_C64_4M also 5 = 256x128, 6 = 128x128 with raised matrix-core priority,
- * 7 = 128x128, 8 = 256x128 and 9 = 128x128 at three waves per SIMD, all
- * direct-to-LDS (operands whose summed indices are their lowest axes).  *n_set (may be NULL) receives the number of
- * contractions changed.  TN_E_INVALID for an unknown variant.  Used to test
+ * TN_C64_4M also 5 = 256x128 and 6 = 128x128 with raised matrix-core
+ * priority; for TN_C64_4M and TN_C64_3M 7 = 128x128, 8 = 256x128 and
+ * 9 = 128x128 at more waves per SIMD, all direct-to-LDS (operands whose
+ * summed indices are their lowest axes).  *n_set (may be NULL) receives the
+ * number of contractions changed.  TN_E_INVALID for an unknown variant.  Used to test
  * every variant and to reproduce a tuned plan.
  */
 int tn_plan_set_tile(tn_plan_t plan, int32_t tile, int32_t* n_set);

@@ -157,6 +157,7 @@ __device__ __forceinline__ void tile_elem(const TileMap& m, uint32_t e, uint64_t
 // ------------------------------------------------------------------ matrix-core GEMMs
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -372,7 +373,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
-  typedef float f4 __attribute__((ext_vector_type(4)));
   f4 fa[2][FM], fb[2][FN];
   auto fread = [&](int buf, int half) {
 #pragma unroll
@@ -409,54 +409,42 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
-// 4M for operands whose summed bits are their lowest positions, in order
-// (k bit i at position i: every intermediate the planner lays out, and most
-// leaves).  Each tile row is then 8 contiguous complex values per stage, so
-// the stage is copied straight from global memory into LDS by
-// global_load_lds_dwordx4 (16 bytes = two complex values per lane, no
-// registers in between), into a ring of three LDS buffers: two stages are in
-// flight while the matrix cores work on the third, with one barrier per stage.
-// LDS keeps the complex values interleaved, 4 units of 16 bytes per row; the
-// unit holding k pair kp of row r sits at r * 4 + (kp ^ ((r >> 2) & 3)), a
-// swizzle applied by choosing which element each lane loads (the lane's LDS
-// slot is fixed), so that the 128-bit fragment reads of 16 lanes hit disjoint
-// banks.  A lane of half hi reads complex k = 4q + 2hi, 4q + 2hi + 1 of its row
-// as (re, im, re, im); the four matrix-core ops of k group q pair the real k
-// indices (re, im, re, im of 4q + {0, 1}) of the lower half with those of
-// 4q + {2, 3} of the upper half, and each lane forms the matching entries of
-// [[Br Bi] [-Bi Br]] from its B unit with selects.
-template <int BM, int BN, int WGM, int WGN, int OCC = 2>
-__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_4m_dl(Ctx ctx, GemmOp op) {
-  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
-  constexpr int WM = BM / WGM, WN = BN / WGN;
-  constexpr int FM = WM / 32, FN = WN / 16;
-  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
-  constexpr int IA = BM * 4 / 64 / NW, IB = BN * 4 / 64 / NW;   // load instructions per wave and stage
-  constexpr int NBUF = 3;
-  constexpr int UNITS = (BM + BN) * 4;                            // 16-byte units per buffer
-  static_assert(FM >= 1 && FN >= 1 && IA >= 1 && IB >= 1, "tile too small");
-  static_assert(IA * NW * 64 == BM * 4 && IB * NW * 64 == BN * 4, "tile / wave mismatch");
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  __shared__ __attribute__((aligned(16))) f4 lds[NBUF * UNITS];
-  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+// Operand ring of the direct-to-LDS kernels, for operands whose summed bits
+// are their lowest positions, in order (k bit i at position i: every
+// intermediate the planner lays out, and most leaves).  Each tile row is then
+// 8 contiguous complex values per stage, so the stage is copied straight from
+// global memory into LDS by global_load_lds_dwordx4 (16 bytes = two complex
+// values per lane, no registers in between), into a ring of three LDS
+// buffers: two stages are in flight while the matrix cores work on the third,
+// with one barrier per stage.  LDS keeps the complex values interleaved, 4
+// units of 16 bytes per row (the BM A rows, then the BN B rows); the unit
+// holding k pair kp of row r sits at r * 4 + (kp ^ ((r >> 2) & 3)), a swizzle
+// applied by choosing which element each lane loads (the lane's LDS slot is
+// fixed), so that the 128-bit fragment reads of 16 lanes on distinct rows
+// hit disjoint banks.
+__device__ __forceinline__ int dl_unit(int r, int kp) { return r * 4 + (kp ^ ((r >> 2) & 3)); }
 
-  GemmSetup g;
-  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
-  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
-                         deposit_runs(g.h, op.run_a_h);
-  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
-                         deposit_runs(g.h, op.run_b_h);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // element offset (tile row, k pair) of every unit this lane loads
-  uint32_t a_off[IA], b_off[IB];          // tensors hold fewer than 2^32 elements
-  {
+template <int BM, int BN, int NW>
+struct DlRing {
+  static constexpr int IA = BM * 4 / 64 / NW, IB = BN * 4 / 64 / NW;   // load instructions per wave and stage
+  static constexpr int NBUF = 3;
+  static constexpr int UNITS = (BM + BN) * 4;                            // 16-byte units per buffer
+  static_assert(IA >= 1 && IB >= 1, "tile too small");
+  static_assert(IA * NW * 64 == BM * 4 && IB * NW * 64 == BN * 4, "tile / wave mismatch");
+  GMEM const float2* A;
+  GMEM const float2* B;
+  uint32_t a_off[IA], b_off[IB];          // element offset (tile row, k pair) of every unit this lane loads
+
+  __device__ __forceinline__ DlRing(const Ctx& ctx, const GemmOp& op, const GemmSetup& g, int wave, int lane) {
+    A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_a_h);
+    B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_b_h);
     const uint64_t mrows = uint64_t(1) << g.tm, nrows = uint64_t(1) << g.tn;
 #pragma unroll
     for (int i = 0; i < IA; i++) {
       const int slot = (wave * IA + i) * 64 + lane;
       const int r = slot >> 2, kp = (slot & 3) ^ ((r >> 2) & 3);
       const uint64_t rr = uint64_t(r) < mrows ? uint64_t(r) : 0;      // rows past a partial tile repeat row 0
-      a_off[i] = (uint32_t)deposit_runs((g.tile_m << g.tm) | rr, op.run_a_m) + 2 * kp;
+      a_off[i] = (uint32_t)deposit_runs((g.tile_m << g.tm) | rr, op.run_a_m) + 2 * kp;   // tensors hold < 2^32 elements
     }
 #pragma unroll
     for (int i = 0; i < IB; i++) {
@@ -466,10 +454,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       b_off[i] = (uint32_t)deposit_runs((g.tile_n << g.tn) | rr, op.run_b_n) + 2 * kp;
     }
   }
-  const uint64_t nsteps = uint64_t(1) << (op.n_k - RK);
-  auto issue = [&](uint64_t step) {
+
+  // start the loads of stage `step` into its ring buffer
+  __device__ __forceinline__ void issue(f4* lds, uint64_t step, int wave) const {
     const int buf = (int)(step % NBUF);
-    const uint32_t k0 = (uint32_t)(step << RK);
+    const uint32_t k0 = (uint32_t)(step << 3);
 #pragma unroll
     for (int i = 0; i < IA; i++)
       __builtin_amdgcn_global_load_lds((GMEM const void*)(A + a_off[i] + k0),
@@ -480,7 +469,43 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       __builtin_amdgcn_global_load_lds((GMEM const void*)(B + b_off[i] + k0),
                                        (__attribute__((address_space(3))) void*)(&lds[buf * UNITS + BM * 4 + (wave * IB + i) * 64]),
                                        16, 0, 0);
-  };
+  }
+
+  // Waits until stage s is in LDS for every wave and every wave is done with
+  // the buffer of stage s - 1 (its fragment reads were consumed by the matrix
+  // cores).  This wave's loads of stage s are done once at most those of
+  // stage s + 1 remain (the direct-to-LDS data is in LDS when its load
+  // retires); then a plain barrier: a fence would also drain the stage s + 1
+  // loads.
+  __device__ __forceinline__ static void wait(bool more) {
+    if (more) __builtin_amdgcn_s_waitcnt((IA + IB) | (0x7 << 4) | (0xF << 8));
+    else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
+    __builtin_amdgcn_s_barrier();
+  }
+};
+
+// 4M on the direct-to-LDS ring.  A lane of half hi reads complex
+// k = 4q + 2hi, 4q + 2hi + 1 of its row as (re, im, re, im); the four
+// matrix-core ops of k group q pair the real k indices (re, im, re, im of
+// 4q + {0, 1}) of the lower half with those of 4q + {2, 3} of the upper half,
+// and each lane forms the matching entries of [[Br Bi] [-Bi Br]] from its B
+// unit with selects.
+template <int BM, int BN, int WGM, int WGN, int OCC = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_4m_dl(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  typedef DlRing<BM, BN, NW> Ring;
+  __shared__ __attribute__((aligned(16))) f4 lds[Ring::NBUF * Ring::UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Ring ring(ctx, op, g, wave, lane);
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - RK);
 
   const int wm = wave / WGN, wn = wave % WGN;
   const int hi = lane >> 5, c32 = lane & 31, p = c32 & 1;
@@ -493,37 +518,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
-  issue(0);
-  if (nsteps > 1) issue(1);
+  ring.issue(lds, 0, wave);
+  if (nsteps > 1) ring.issue(lds, 1, wave);
   for (uint64_t s = 0; s < nsteps; s++) {
-    // this wave's loads of stage s are done once at most those of stage s + 1
-    // remain (the direct-to-LDS data is in LDS when its load retires)
-    if (s + 1 < nsteps) __builtin_amdgcn_s_waitcnt((IA + IB) | (0x7 << 4) | (0xF << 8));
-    else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
-    // every wave's stage s has landed and every wave is done with the buffer
-    // of stage s - 1 (its fragment reads were consumed by the matrix cores);
-    // a plain barrier: a fence here would also drain the stage s + 1 loads
-    __builtin_amdgcn_s_barrier();
-    if (s + 2 < nsteps) issue(s + 2);
-    const f4* L = &lds[(int)(s % NBUF) * UNITS];
+    Ring::wait(s + 1 < nsteps);
+    if (s + 2 < nsteps) ring.issue(lds, s + 2, wave);
+    const f4* L = &lds[(int)(s % Ring::NBUF) * Ring::UNITS];
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const int kp = 2 * q + hi;
       f4 fa[FM];
 #pragma unroll
       for (int i = 0; i < FM; i++) {
-        const int r = wm * WM + i * 32 + c32;
-        fa[i] = L[r * 4 + (kp ^ ((r >> 2) & 3))];
+        fa[i] = L[dl_unit(wm * WM + i * 32 + c32, kp)];
         fa[i][1] *= sa;
         fa[i][3] *= sa;
       }
       // one B fragment at a time (fewer live registers), the next one read
       // while the matrix cores work on this one; consecutive matrix-core ops
       // alternate between the FM accumulators of column block j
-      auto bunit = [&](int j) {
-        const int n = wn * WN + j * 16 + (c32 >> 1);
-        return L[BM * 4 + n * 4 + (kp ^ ((n >> 2) & 3))];
-      };
+      auto bunit = [&](int j) { return L[BM * 4 + dl_unit(wn * WN + j * 16 + (c32 >> 1), kp)]; };
       f4 u = bunit(0);
 #pragma unroll
       for (int j = 0; j < FN; j++) {
@@ -545,6 +559,50 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   }
   __syncthreads();                         // the epilogue reuses the LDS ring for its tables
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
+}
+
+// Epilogue of the 3M kernels: with T1, T2, T3 the three real accumulator
+// planes of a 32 x 32 complex tile (lane l holds complex column l % 32, rows
+// 8 (r / 4) + 4 (l / 32) + r % 4), C = (T1 - T2) + i (T3 - T1 - T2) at
+// deposit(row, c_m) + deposit(col, c_n) (+ batch).
+template <int BM, int BN, int FM, int FN>
+__device__ __forceinline__ void gemm_store_3m(const Ctx& ctx, const GemmOp& op, const GemmSetup& g, uint64_t* tab,
+                                              const floatx16 (&acc)[3][FM][FN], int wm, int wn, int tid, int nthreads) {
+  constexpr int WM = FM * 32, WN = FN * 32;
+  GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
+  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
+                         deposit_runs(g.tile_n << g.tn, op.run_c_n);
+  uint64_t* rowoff = tab;
+  uint64_t* coloff = tab + BM;
+  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
+  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, 0, g.tn);
+  __syncthreads();
+  const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31;
+  const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      const int col = wn * WN + j * 32 + c32;
+      if (col >= nvalid) continue;
+      const uint64_t co = coloff[col];
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+        if (row >= mvalid) continue;
+        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+        float2 v;
+        v.x = t1 - t2;
+        v.y = t3 - t1 - t2;
+        GMEM float2* dst = C + cbase + rowoff[row] + co;
+        if (op.accumulate) {
+          const float2 o = ld(dst);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        st(dst, v);
+      }
+    }
 }
 
 // 3M (Gauss) on FP32 matrix cores: with T1 = Ar Br, T2 = Ai Bi and
@@ -647,7 +705,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       for (int j = 0; j < FN; j++)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[t][i][j][r] = 0.f;
-  typedef float f4 __attribute__((ext_vector_type(4)));
 
   gload();
   sstore(0);
@@ -676,40 +733,88 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
   }
 
-  // epilogue: lane holds complex column c32 of each 32 x 32 tile
-  GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
-                         deposit_runs(g.tile_n << g.tn, op.run_c_n);
-  uint64_t* rowoff = reinterpret_cast<uint64_t*>(&lds[0][0][0][0]);
-  uint64_t* coloff = rowoff + BM;
-  for (int i = tid; i < BM; i += NT) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
-  for (int i = tid; i < BN; i += NT) coloff[i] = deposit(i, op.c_n, 0, g.tn);
-  __syncthreads();
-  const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
+  gemm_store_3m<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
+}
+
+// 3M on the direct-to-LDS ring of the 4M kernel: the ring holds the raw
+// (re, im) units and each lane forms the re + im plane of its fragments in
+// registers.  A lane of half hi reads complex k = 4q + 2hi, 4q + 2hi + 1 of
+// its A row and of its B column; matrix-core op e of k group q pairs complex
+// k = 4q + e (lower half) with 4q + 2 + e (upper half) in each of the three
+// real planes, 12 ops per 32 x 32 complex tile and stage (the 4M kernel
+// takes 16).  Each wave holds WM x WN complex outputs.
+template <int BM, int BN, int WGM, int WGN, int OCC = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_3m_dl(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  typedef DlRing<BM, BN, NW> Ring;
+  __shared__ __attribute__((aligned(16))) f4 lds[Ring::NBUF * Ring::UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Ring ring(ctx, op, g, wave, lane);
+  const uint64_t nsteps = uint64_t(1) << (op.n_k - RK);
+
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int hi = lane >> 5, c32 = lane & 31;
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  floatx16 acc[3][FM][FN];
 #pragma unroll
-  for (int i = 0; i < FM; i++)
+  for (int t = 0; t < 3; t++)
 #pragma unroll
-    for (int j = 0; j < FN; j++) {
-      const int col = wn * WN + j * 32 + c32;
-      if (col >= nvalid) continue;
-      const uint64_t co = coloff[col];
+    for (int i = 0; i < FM; i++)
 #pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-        if (row >= mvalid) continue;
-        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
-        float2 v;
-        v.x = t1 - t2;
-        v.y = t3 - t1 - t2;
-        GMEM float2* dst = C + cbase + rowoff[row] + co;
-        if (op.accumulate) {
-          const float2 o = ld(dst);
-          v.x += o.x;
-          v.y += o.y;
-        }
-        st(dst, v);
+      for (int j = 0; j < FN; j++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[t][i][j][r] = 0.f;
+
+  ring.issue(lds, 0, wave);
+  if (nsteps > 1) ring.issue(lds, 1, wave);
+  for (uint64_t s = 0; s < nsteps; s++) {
+    Ring::wait(s + 1 < nsteps);
+    if (s + 2 < nsteps) ring.issue(lds, s + 2, wave);
+    const f4* L = &lds[(int)(s % Ring::NBUF) * Ring::UNITS];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int kp = 2 * q + hi;
+      f4 fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; i++) {
+        fa[i] = L[dl_unit(wm * WM + i * 32 + c32, kp)];
+        fa[i][1] *= sa;
+        fa[i][3] *= sa;
+      }
+#pragma unroll
+      for (int j = 0; j < FN; j++) {
+        fb[j] = L[BM * 4 + dl_unit(wn * WN + j * 32 + c32, kp)];
+        fb[j][1] *= sb;
+        fb[j][3] *= sb;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        float pa[FM], pb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; i++) pa[i] = fa[i][2 * e] + fa[i][2 * e + 1];
+#pragma unroll
+        for (int j = 0; j < FN; j++) pb[j] = fb[j][2 * e] + fb[j][2 * e + 1];
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int j = 0; j < FN; j++) {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][2 * e], fb[j][2 * e], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][2 * e + 1], fb[j][2 * e + 1], acc[1][i][j], 0, 0, 0);
+            acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[i], pb[j], acc[2][i][j], 0, 0, 0);
+          }
       }
     }
+  }
+  __syncthreads();                         // the epilogue reuses the LDS ring for its tables
+  gemm_store_3m<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
 // bf16 round-to-nearest-even of a finite float, and back
@@ -1062,9 +1167,9 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 4: *bm = 6; *bn = 6; return 0;     // vector-ALU 64 x 64
     case 5: *bm = 8; *bn = 7; return 0;     // 256 x 128, 8 waves (4M only)
     case 6: *bm = 7; *bn = 7; return 0;     // 128 x 128 with raised matrix-core priority (4M only)
-    case 7: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring (4M, summed bits lowest)
+    case 7: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring (4M / 3M, summed bits lowest)
     case 8: *bm = 8; *bn = 7; return 0;     // 256 x 128 direct-to-LDS ring, 8 waves
-    case 9: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring, 3 waves per SIMD
+    case 9: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring, 3 (4M) / 4 (3M) waves per SIMD
     default: return -1;
   }
 }
@@ -1074,7 +1179,7 @@ bool gemm_tile_ok(const GemmOp& op, int tile, int prec) {
   if (gemm_tile_bits(tile, &bm, &bn)) return false;
   if (prec == TN_C128) return tile == kValuTile;
   if (tile < kNumTilesShared || tile == kValuTile) return true;
-  if (prec != TN_C64_4M) return false;
+  if (prec == TN_C64_3M ? (tile != 7 && tile != 8 && tile != 9) : prec != TN_C64_4M) return false;
   if (tile >= 7) {
     // the summed bits must be the lowest positions of both operands, in order
     if (op.n_k < 3) return false;
@@ -1117,6 +1222,10 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s
       case 1: hipLaunchKernelGGL((gemm_mfma_3m<64, 128, 1, 4>), grid, dim3(256), 0, s, ctx, op); break;
       case 2: hipLaunchKernelGGL((gemm_mfma_3m<128, 64, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
       case 3: hipLaunchKernelGGL((gemm_mfma_3m<64, 64, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
+      // direct-to-LDS ring: waves of 64 x 64 (7, 8) or 64 x 32 (9)
+      case 7: hipLaunchKernelGGL((gemm_mfma_3m_dl<128, 128, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
+      case 8: hipLaunchKernelGGL((gemm_mfma_3m_dl<256, 128, 4, 2>), grid, dim3(512), 0, s, ctx, op); break;
+      case 9: hipLaunchKernelGGL((gemm_mfma_3m_dl<128, 128, 2, 4, 4>), grid, dim3(512), 0, s, ctx, op); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -148,3 +148,36 @@ def test_cfg4_gradient_full_size(oracle_lib):
     refv = np.concatenate([r.ravel() for r in ref])
     note("cfg4 sub-slice gradient rel err", rel(got, refv))
     assert rel(got, refv) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c64_3m"])
+def test_backward_direct_to_lds(oracle_lib, prec):
+    """Gradient contractions on the direct-to-LDS matrix-core variants: with
+    A(M, K) or A(K, M) and B(K, N) the gradient of A sums N, the lowest axes
+    of both the cotangent and B, and reads B conjugated."""
+    import torch
+
+    from tests.gpu_util import TOL_3M
+    from tn_inputs.network import Network, Tree
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    tol = TOL_3M if prec == "c64_3m" else TOL_C64
+    m, n, k = 8, 9, 7
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    for case, ia in (("MK,KN", M + K), ("KM,KN", K + M)):
+        rng = np.random.default_rng(len(case) + len(ia))
+        a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+        b = rng.normal(size=(2,) * (k + n)) + 1j * rng.normal(size=(2,) * (k + n))
+        net = Network([a, b], [ia, K + N], [2] * (m + n + k), M + N)
+        go = rng.normal(size=(2,) * (m + n)) + 1j * rng.normal(size=(2,) * (m + n))
+        refs = oracle_lib.grad(net, two, go, [0, 1])
+        ref = np.concatenate([r.ravel() for r in refs])
+        for t in (7, 8, 9):
+            plan = _plan(net, two, precision=prec)
+            plan.backward_info([0, 1])
+            changed = plan.set_tile(t)
+            note("backward dl", prec, case, "tile", t, "changed", changed)
+            assert changed >= 1
+            grads = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0, 1])
+            torch.cuda.synchronize()
+            got = np.concatenate([g.cpu().numpy().ravel() for g in grads])
+            assert rel(got, ref) < tol, (case, t)
