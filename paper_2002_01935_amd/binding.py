@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtn.so")
 
 TN_C64_4M, TN_C64_3M, TN_C64_BF16X3, TN_C128 = 0, 1, 2, 3
 PRECISIONS = {"c64_4m": TN_C64_4M, "c64_3m": TN_C64_3M, "c64_bf16x3": TN_C64_BF16X3, "c128": TN_C128}
-KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm"}
+KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm", 3: "gemm_splitk"}
 
 EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",

@@ -544,13 +544,14 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     float best_ms = 1e30f;
     int best_tile = 0;
     // matrix-core tiles only; the summed range is cut to at most 2^9 values
-    // for the trials (time per tile scales with K, the ranking does not)
+    // per split for the trials (time per tile scales with K, the ranking does
+    // not)
     const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
     for (int t = 0; t < kNumGemmTiles; t++) {
       if (t == kValuTile || !gemm_tile_ok(g, t, p->prec)) continue;
       GemmOp trial = g;
       trial.tile = t;
-      trial.n_k = std::min(trial.n_k, 9);
+      trial.n_k = std::min(trial.n_k, 9 + std::max(0, trial.k_split_bits));
       const int reps = 2;
       HIP_TRY(launch_gemm(ctx, trial, p->prec, s));   // warm-up
       HIP_TRY(hipEventRecord(e0, s));

@@ -189,6 +189,7 @@ struct GemmSetup {
   uint64_t tile_m, tile_n, h;
   int z;
   int64_t sid;
+  uint64_t ka, kb, cs;   // split-K offsets of this block's summed range in A and B, and of its partial tile
 };
 
 __device__ __forceinline__ bool gemm_setup(const Ctx& ctx, const GemmOp& op, int rm, int rn, int rk, GemmSetup& g) {
@@ -214,6 +215,9 @@ __device__ __forceinline__ bool gemm_setup(const Ctx& ctx, const GemmOp& op, int
   const uint64_t r = t & (in_group - 1);
   g.tile_m = ((t >> (op.n_n - g.tn + gm_bits)) << gm_bits) + (r & ((uint64_t(1) << gm_bits) - 1));
   g.tile_n = r >> gm_bits;
+  g.ka = deposit_runs(blockIdx.z, op.run_a_s);
+  g.kb = deposit_runs(blockIdx.z, op.run_b_s);
+  g.cs = uint64_t(blockIdx.z) << op.c_split_shift;
   return true;
 }
 
@@ -226,7 +230,7 @@ __device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, con
                                            const floatx16 (&acc)[FM][FN], int wm, int wn, int tid, int nthreads) {
   constexpr int WM = FM * 32, WN = FN * 16;
   GMEM float* C = reinterpret_cast<GMEM float*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
+  const uint64_t cbase = g.cs + deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
                          deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
@@ -297,9 +301,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
-  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + g.ka +
                          deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
-  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + g.kb +
                          deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
@@ -436,8 +440,8 @@ struct DlRing {
   uint32_t a_off[IA], b_off[IB];          // element offset (tile row, k pair) of every unit this lane loads
 
   __device__ __forceinline__ DlRing(const Ctx& ctx, const GemmOp& op, const GemmSetup& g, int wave, int lane) {
-    A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_a_h);
-    B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_b_h);
+    A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_a_h) + g.ka;
+    B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + deposit_runs(g.h, op.run_b_h) + g.kb;
     const uint64_t mrows = uint64_t(1) << g.tm, nrows = uint64_t(1) << g.tn;
 #pragma unroll
     for (int i = 0; i < IA; i++) {
@@ -570,7 +574,7 @@ __device__ __forceinline__ void gemm_store_3m(const Ctx& ctx, const GemmOp& op, 
                                               const floatx16 (&acc)[3][FM][FN], int wm, int wn, int tid, int nthreads) {
   constexpr int WM = FM * 32, WN = FN * 32;
   GMEM float2* C = reinterpret_cast<GMEM float2*>(resolve(ctx, op.c, g.z, g.sid, 8));
-  const uint64_t cbase = deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
+  const uint64_t cbase = g.cs + deposit_runs(g.h, op.run_c_h) + deposit_runs(g.tile_m << g.tm, op.run_c_m) +
                          deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
@@ -628,9 +632,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
-  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + g.ka +
                          deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
-  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + g.kb +
                          deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
@@ -849,9 +853,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 
   GemmSetup g;
   if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
-  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) +
+  GMEM const float2* A = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.a, g.z, g.sid, 8)) + g.ka +
                          deposit_runs(g.h, op.run_a_h) + deposit_runs(g.tile_m << g.tm, op.run_a_m);
-  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) +
+  GMEM const float2* B = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.b, g.z, g.sid, 8)) + g.kb +
                          deposit_runs(g.h, op.run_b_h) + deposit_runs(g.tile_n << g.tn, op.run_b_n);
   const int tid = threadIdx.x;
   uint32_t a_off[LA], b_off[LB];
@@ -987,6 +991,46 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
 }
 
+// ------------------------------------------------------------------ split-K sum
+
+// Fixed-order sum of the split-K partial products of a GEMM (splits in
+// increasing order, so the result does not depend on scheduling): element e
+// = (h, m, n) of every split, n fastest, goes to C at the positions of its h,
+// m and n bits.
+struct SplitReduceOp {
+  Ref part, c;
+  BitRuns run_c;       // C positions of the bits of e
+  int32_t n_e;         // log2 elements per split
+  int32_t n_split;     // log2 splits
+  int32_t accumulate;  // add into C instead of overwriting
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void split_reduce_kernel(Ctx ctx, SplitReduceOp op) {
+  using V = typename C2<T>::t;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const uint64_t e = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >> op.n_e) return;
+  GMEM const V* P = reinterpret_cast<GMEM const V*>(resolve(ctx, op.part, z, sid, sizeof(V))) + e;
+  V acc = ld(P);
+  const uint64_t ns = uint64_t(1) << op.n_split;
+#pragma unroll 8
+  for (uint64_t sp = 1; sp < ns; sp++) {
+    const V v = ld(P + (sp << op.n_e));
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, sizeof(V))) + deposit_runs(e, op.run_c);
+  if (op.accumulate) {
+    const V o = ld(C);
+    acc.x += o.x;
+    acc.y += o.y;
+  }
+  st(C, acc);
+}
+
 // ------------------------------------------------------------------ VALU tiled GEMM
 
 // 64 x 64 complex tile, 256 threads, each thread 4 x 4 outputs; used for
@@ -1010,11 +1054,12 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   const uint64_t tile_m = blockIdx.x / ntiles_n, tile_n = blockIdx.x % ntiles_n;
   const int eb = sizeof(V);
   GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit_runs(h, op.run_a_h) +
-               deposit_runs(tile_m << tm, op.run_a_m);
+               deposit_runs(tile_m << tm, op.run_a_m) + deposit_runs(blockIdx.z, op.run_a_s);
   GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit_runs(h, op.run_b_h) +
-               deposit_runs(tile_n << tn, op.run_b_n);
+               deposit_runs(tile_n << tn, op.run_b_n) + deposit_runs(blockIdx.z, op.run_b_s);
   GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit_runs(h, op.run_c_h) +
-         deposit_runs(tile_m << tm, op.run_c_m) + deposit_runs(tile_n << tn, op.run_c_n);
+         deposit_runs(tile_m << tm, op.run_c_m) + deposit_runs(tile_n << tn, op.run_c_n) +
+         (uint64_t(blockIdx.z) << op.c_split_shift);
   TileMap ma, mb;
   make_tilemap(ma, op.a_m, tm, op.a_k, tk, RM);
   make_tilemap(mb, op.b_n, tn, op.b_k, tk, RN);
@@ -1189,8 +1234,29 @@ bool gemm_tile_ok(const GemmOp& op, int tile, int prec) {
   return true;
 }
 
+static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec, dim3 grid, hipStream_t s);
+
 hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s) {
   GemmOp op = in;
+  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+  const int e_bits = op.n_h + op.n_m + op.n_n;
+  op.run_a_s.n = 0;
+  op.run_b_s.n = 0;
+  op.c_split_shift = 0;
+  if (ks) {
+    // the kernels sum the low n_k - ks summed bits; split z adds the top ks
+    // bits' offsets and writes its tile to part[z][h][m][n]
+    if (ks >= op.n_k || e_bits + ks > 40 || ks > 10) return hipErrorInvalidValue;
+    op.n_k -= ks;
+    make_runs(op.a_k + op.n_k, ks, op.run_a_s);
+    make_runs(op.b_k + op.n_k, ks, op.run_b_s);
+    op.c = op.part;
+    op.accumulate = 0;
+    for (int j = 0; j < op.n_n; j++) op.c_n[j] = (int8_t)j;
+    for (int i = 0; i < op.n_m; i++) op.c_m[i] = (int8_t)(op.n_n + i);
+    for (int i = 0; i < op.n_h; i++) op.c_h[i] = (int8_t)(op.n_n + op.n_m + i);
+    op.c_split_shift = e_bits;
+  }
   make_runs(op.a_h, op.n_h, op.run_a_h);
   make_runs(op.b_h, op.n_h, op.run_b_h);
   make_runs(op.c_h, op.n_h, op.run_c_h);
@@ -1201,12 +1267,33 @@ hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s
   int bm, bn;
   int tile = op.tile;
   if (prec == TN_C128) tile = 4;
+  op.tile = tile;
   if (gemm_tile_bits(tile, &bm, &bn) || !gemm_tile_ok(op, tile, prec)) return hipErrorInvalidValue;
   const int tm = op.n_m < bm ? op.n_m : bm, tn = op.n_n < bn ? op.n_n : bn;
   const uint64_t tiles = uint64_t(1) << ((op.n_m - tm) + (op.n_n - tn));
   const uint64_t gy = uint64_t(ctx.n_batch) << op.n_h;
   if (tiles > 0x7fffffffULL || gy > 65535) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)tiles, (unsigned)gy);
+  hipError_t err = launch_gemm_kernel(ctx, op, prec, dim3((unsigned)tiles, (unsigned)gy, 1u << ks), s);
+  if (err != hipSuccess || !ks) return err;
+  SplitReduceOp r;
+  r.part = in.part;
+  r.c = in.c;
+  r.n_e = e_bits;
+  r.n_split = ks;
+  r.accumulate = in.accumulate;
+  int8_t pos[kMaxBits];
+  for (int j = 0; j < in.n_n; j++) pos[j] = in.c_n[j];
+  for (int i = 0; i < in.n_m; i++) pos[in.n_n + i] = in.c_m[i];
+  for (int i = 0; i < in.n_h; i++) pos[in.n_n + in.n_m + i] = in.c_h[i];
+  make_runs(pos, e_bits, r.run_c);
+  dim3 rg(blocks_for(uint64_t(1) << e_bits, 256), ctx.n_batch);
+  if (prec == TN_C128) hipLaunchKernelGGL(split_reduce_kernel<double>, rg, dim3(256), 0, s, ctx, r);
+  else hipLaunchKernelGGL(split_reduce_kernel<float>, rg, dim3(256), 0, s, ctx, r);
+  return hipGetLastError();
+}
+
+static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec, dim3 grid, hipStream_t s) {
+  const int tile = op.tile;
   if (prec == TN_C128) {
     hipLaunchKernelGGL(gemm_valu<double>, grid, dim3(256), 0, s, ctx, op);
     return hipGetLastError();

@@ -385,6 +385,13 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     for (int i = 0; i < fb; i++) { g.b_n[i] = (int8_t)B.lay.pos_of(FB[i]); g.c_n[i] = (int8_t)posC(FB[i]); }
     for (int i = 0; i < k; i++) { g.a_k[i] = (int8_t)A.lay.pos_of(K[i]); g.b_k[i] = (int8_t)B.lay.pos_of(K[i]); }
     op.grid_rows = int64_t(1) << (h + fa + fb);
+    // few output tiles and a long sum: the top summed bits go to the grid
+    // (about 2^9 blocks of 128 x 128 tiles, each summing at least 2^9 values),
+    // the partial tiles to an arena buffer summed in a fixed order afterwards
+    const int tiles_log = std::max(0, fa - 7) + std::max(0, fb - 7) + h;
+    const int ks = std::min(std::min(k - 9, 9 - tiles_log), 10);
+    g.k_split_bits = ks > 0 ? ks : 0;
+    if (ks > 0) g.part = buf_ref(prog.new_buf((int64_t)p->elem_bytes << (h + fa + fb + ks)));
   } else {
     op.kind = OpKind::Row;
     RowOp& r = op.row;
@@ -440,6 +447,7 @@ static void push(Prog& prog, Op op) {
     if (op.row.k_split_bits > 0) prog.touch(op.row.part, idx);
   } else if (op.kind == OpKind::Gemm) {
     prog.touch(op.gemm.a, idx); prog.touch(op.gemm.b, idx); prog.touch(op.gemm.c, idx);
+    if (op.gemm.k_split_bits > 0) prog.touch(op.gemm.part, idx);
   } else if (op.kind == OpKind::Accum) {
     prog.touch(op.accum.src, idx); prog.touch(op.accum.dst, idx);
   } else if (op.kind == OpKind::Permute) {
@@ -603,7 +611,10 @@ static uint64_t allocate(Prog& prog) {
         fix(op.row.a); fix(op.row.b); fix(op.row.c);
         if (op.row.k_split_bits > 0) fix(op.row.part);
         break;
-      case OpKind::Gemm: fix(op.gemm.a); fix(op.gemm.b); fix(op.gemm.c); break;
+      case OpKind::Gemm:
+        fix(op.gemm.a); fix(op.gemm.b); fix(op.gemm.c);
+        if (op.gemm.k_split_bits > 0) fix(op.gemm.part);
+        break;
       case OpKind::Accum: fix(op.accum.src); fix(op.accum.dst); break;
       case OpKind::Permute: fix(op.perm.src); fix(op.perm.dst); break;
       default: break;
@@ -657,7 +668,8 @@ int build_plan(tn_plan_s* p, std::string& err) {
     Op op = make_contract(p, A, B, 0, 0, buf_ref(bufs[v]), p->layout[v], false, ni.swap ? 1 : 0, v, prog);
     ni.flops = op.flops;
     ni.bytes = op.bytes;
-    ni.kclass = op.kind == OpKind::Gemm ? kGemm : (op.row.k_split_bits >= 0 ? kSplitK : kRow);
+    ni.kclass = op.kind == OpKind::Gemm ? (op.gemm.k_split_bits > 0 ? kGemmSplitK : kGemm)
+                                        : (op.row.k_split_bits >= 0 ? kSplitK : kRow);
     ni.k_split_bits = op.row.k_split_bits;
     push(prog, op);
   }

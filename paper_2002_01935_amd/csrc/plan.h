@@ -13,7 +13,7 @@ namespace tn {
 
 enum class OpKind { Row, RowReduce, Gemm, Accum, Permute, Fill, Counter };
 
-enum KernelClass { kRow = 0, kSplitK = 1, kGemm = 2 };
+enum KernelClass { kRow = 0, kSplitK = 1, kGemm = 2, kGemmSplitK = 3 };
 
 struct Op {
   Op() { std::memset(&row, 0, sizeof row); std::memset(&gemm, 0, sizeof gemm);

@@ -92,6 +92,16 @@ struct GemmOp {
   int8_t a_k[kMaxBits], b_k[kMaxBits];
   BitRuns run_a_h, run_b_h, run_c_h;     // a_h / b_h / c_h as runs
   BitRuns run_a_m, run_c_m, run_b_n, run_c_n;
+  // Split-K: the top k_split_bits summed bits are enumerated by the grid's z
+  // dimension; each split writes its partial product to `part`, laid out
+  // [split][h][m][n] with n fastest, and a fixed-order sum over the splits
+  // produces C.  Set at launch for the kernels: the positions of the split
+  // bits in A and B as runs, and the element stride between splits of the
+  // partial buffer (0 when the grid's z dimension is 1).
+  Ref part;
+  int32_t k_split_bits;
+  int32_t c_split_shift;
+  BitRuns run_a_s, run_b_s;
 };
 
 // Fixed-order FP64 accumulation of each in-flight slice's root into dst.

@@ -181,3 +181,31 @@ def test_backward_direct_to_lds(oracle_lib, prec):
             torch.cuda.synchronize()
             got = np.concatenate([g.cpu().numpy().ravel() for g in grads])
             assert rel(got, ref) < tol, (case, t)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64_4m", "c64_3m"])
+def test_backward_split_k(oracle_lib, prec):
+    """A(M, K) x B(K, N) with a small A and a long free side of B: the
+    gradient of A sums 2^14 values into 2^12 outputs, a split-K GEMM whose
+    partial tiles are summed in a fixed order (twice: bitwise repeatable)."""
+    import torch
+
+    from tests.gpu_util import TOL_3M
+    from tn_inputs.network import Network, Tree
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    tol = {"c128": TOL_C128, "c64_4m": TOL_C64, "c64_3m": TOL_3M}[prec]
+    m, k, n = 6, 6, 14
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(7)
+    a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+    b = rng.normal(size=(2,) * (k + n)) + 1j * rng.normal(size=(2,) * (k + n))
+    net = Network([a, b], [M + K, K + N], [2] * (m + n + k), M + N)
+    go = rng.normal(size=(2,) * (m + n)) + 1j * rng.normal(size=(2,) * (m + n))
+    ref = oracle_lib.grad(net, two, go, [0])[0]
+    plan = _plan(net, two, precision=prec)
+    note("backward split-k", prec)
+    g1 = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0])[0].cpu().numpy()
+    g2 = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0])[0].cpu().numpy()
+    torch.cuda.synchronize()
+    assert rel(g1, ref) < tol
+    assert np.array_equal(g1, g2)

@@ -193,3 +193,34 @@ def test_repeat_is_bitwise_identical():
     a = gpu_sliced(net, tree, plan=p)
     b = gpu_sliced(net, tree, plan=p)
     assert np.array_equal(a, b)
+
+
+SPLIT_SHAPES = [(0, 8, 7, 11), (1, 6, 8, 12), (0, 7, 6, 14), (2, 5, 5, 13)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c64_3m", "c64_bf16x3", "c128"])
+def test_gemm_split_k(oracle_lib, prec):
+    """GEMM nodes with few output tiles and a long sum: the summed range is
+    split across the grid and the partial tiles summed in a fixed order.
+    Random axis orders (split bits scattered in both operands), canonical
+    operands (direct-to-LDS kernels), unsliced direct writes of the output,
+    and a sliced summed index with two slices in flight (one partial buffer
+    per slice)."""
+    from paper_2002_01935_amd.binding import Plan
+    cases = [(pairwise_network(*s, seed=31 + i), f"perm {s}") for i, s in enumerate(SPLIT_SHAPES)]
+    cases += [(_canonical_pair(0, 7, 7, 12, seed=5), "canonical"), (_canonical_pair(1, 6, 7, 11, seed=6), "canonical h")]
+    for net, name in cases:
+        note("split-k", prec, name)
+        plan = Plan(net, TWO, precision=prec)
+        assert [n["kclass"] for n in plan.nodes()] == ["gemm_splitk"], name
+        ref = oracle_lib.contract(net, TWO)
+        assert rel(gpu_sliced(net, TWO, precision=prec, plan=plan), ref) < TOLS[prec], name
+        assert rel(gpu_contract(net, TWO, precision=prec), ref) < TOLS[prec], name
+    net = pairwise_network(0, 8, 7, 12, seed=40, dims=(2,))
+    k_idx = [e for e in range(net.n_idx) if e not in net.out_idx]
+    sl = k_idx[:1]
+    plan = Plan(net, TWO, sliced=sl, precision=prec, max_inflight_slices=2)
+    assert [n["kclass"] for n in plan.nodes()] == ["gemm_splitk"]
+    ref = oracle_lib.contract(net, TWO, sliced=sl)
+    note("split-k sliced", prec)
+    assert rel(gpu_sliced(net, TWO, sliced=sl, precision=prec, max_inflight=2), ref) < TOLS[prec]

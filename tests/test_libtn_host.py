@@ -60,7 +60,7 @@ def test_node_classes(B):
     assert len(nodes) == 119
     for n in nodes:
         big = min(n["logM"], n["logN"]) >= 5
-        assert (n["kclass"] == "gemm") == big
+        assert n["kclass"].startswith("gemm") == big
         assert n["flops"] == 8 * 2 ** (n["logH"] + n["logM"] + n["logN"] + n["logK"])
 
 
@@ -146,3 +146,18 @@ def test_set_tile(B):
     with pytest.raises(B.TNError) as e:
         p.set_tile(99)
     assert e.value.code == -1
+
+
+def test_split_k_gemm_plan(B):
+    # few output tiles and at least 2^10 summed values: the GEMM node is split
+    # across the grid and its workspace holds the partial tiles
+    from tn_inputs.graphs import pairwise_network
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    p = B.Plan(_canonical_pair(7, 7, 14), two)
+    assert [n["kclass"] for n in p.nodes()] == ["gemm_splitk"]
+    # 2^5 splits (top summed bits) of the 2^14 complex64 outputs
+    assert p.info()["workspace_bytes"] >= 8 << (14 + 5)
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(7, 7, 9), two).nodes()] == ["gemm"]
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(10, 10, 14), two).nodes()] == ["gemm_splitk"]   # 64 tiles
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 14), two).nodes()] == ["gemm"]
+    assert [n["kclass"] for n in B.Plan(pairwise_network(0, 8, 7, 11, seed=1), two).nodes()] == ["gemm_splitk"]
