@@ -1173,19 +1173,9 @@ static hipError_t launch_row_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The run tables of an op's position lists (filled here, once per launch or
-// graph capture, so every op the planner makes carries them).
 static RowOp with_runs(const RowOp& in) {
   RowOp op = in;
-  make_runs(op.row_a, op.n_rows, op.run_a);
-  make_runs(op.row_b, op.n_rows, op.run_b);
-  make_runs(op.row_c, op.n_rows, op.run_c);
-  // staged stores: complex64, no accumulation, the in-thread values at C's
-  // lowest positions and the six lane bits of the row right above them
-  bool st = op.k_split_bits < 0 && op.pair_c && !op.accumulate && op.n_in >= 1 && op.n_rows >= 6;
-  for (int i = 0; st && i < op.n_in; i++) st = op.in_c[i] == i;
-  for (int i = 0; st && i < 6; i++) st = op.row_c[i] == op.n_in + i;
-  op.stage_c = st ? 1 : 0;
+  prepare_row(op);
   return op;
 }
 

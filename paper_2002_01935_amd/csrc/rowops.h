@@ -108,11 +108,19 @@ __device__ __forceinline__ GMEM char* resolve(const Ctx& ctx, const Ref& r, int 
     return reinterpret_cast<GMEM char*>(ctx.ws + ctx.arena_off + uint64_t(z) * ctx.arena_stride + r.off);
   const uint64_t p = reinterpret_cast<CMEM const uint64_t*>(ctx.ws + ctx.ptrtab_off)[r.slot];
   uint64_t off = 0;
-  for (int i = 0; i < r.n_slice; i++) {
-    const uint32_t wb = reinterpret_cast<const uint32_t*>(r.slice_bit)[i >> 2];
-    const uint32_t wp = reinterpret_cast<const uint32_t*>(r.slice_pos)[i >> 2];
+  // the term lists are read as one batch; the work stops at n_slice
+  const int ns = r.n_slice;
+  uint32_t wb[kMaxSliceTerms / 4], wp[kMaxSliceTerms / 4];
+#pragma unroll
+  for (int i = 0; i < kMaxSliceTerms / 4; i++) {
+    wb[i] = reinterpret_cast<const uint32_t*>(r.slice_bit)[i];
+    wp[i] = reinterpret_cast<const uint32_t*>(r.slice_pos)[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxSliceTerms; i++) {
+    if (i >= ns) break;
     const int sh = 8 * (i & 3);
-    off |= uint64_t((sid >> ((wb >> sh) & 0xFF)) & 1) << ((wp >> sh) & 0xFF);
+    off |= uint64_t((sid >> ((wb[i >> 2] >> sh) & 0xFF)) & 1) << ((wp[i >> 2] >> sh) & 0xFF);
   }
   return reinterpret_cast<GMEM char*>(p) + off * uint64_t(ebytes);
 }
@@ -128,11 +136,6 @@ __device__ __forceinline__ V conjv(V a, int c) {
 constexpr int kRowThreads = 256;
 
 // Offsets below are 32-bit: the planner rejects tensors of 2^32 elements or more.
-__device__ __forceinline__ uint32_t dep32(uint32_t v, const int8_t* pos, int first, int n) {
-  uint32_t off = 0;
-  for (int i = 0; i < n; i++) off |= ((v >> i) & 1u) << pos_at(pos, first + i);
-  return off;
-}
 
 // Deposit of an index through the runs of its position list: one
 // shift-and-mask per run (the run table is read at uniform addresses).
@@ -145,14 +148,34 @@ __device__ __forceinline__ uint64_t deposit_runs(uint64_t v, const BitRuns& R) {
   }
   return off;
 }
+// The first eight entries are read as one batch of scalar loads; the
+// per-lane work stops at the table's length (a uniform branch).
 __device__ __forceinline__ uint32_t deposit_runs32(uint32_t v, const BitRuns& R) {
   uint32_t off = 0;
-  for (int i = 0; i < R.n; i++) {
-    const uint32_t w = R.r[i];
+  auto piece = [&](uint32_t w) {
     const uint32_t src = w & 0xFF, dst = (w >> 8) & 0xFF, len = w >> 16;
-    off |= ((v >> src) & (~0u >> (32 - len))) << dst;
+    return ((v >> src) & (~0u >> (32 - len))) << dst;
+  };
+  const int n = R.n;
+  uint32_t w[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) w[i] = R.r[i];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (i >= n) return off;
+    off |= piece(w[i]);
   }
+  for (int i = 8; i < n; i++) off |= piece(R.r[i]);
   return off;
+}
+
+// Offset change of a summed-bit walk from counter value c to c + 1, from the
+// op's carry table (the carry bit is clamped to the walk's n bits, so the
+// last step of a walk is harmless and needs no guard).
+__device__ __forceinline__ uint32_t kstep(const uint32_t* tab, uint32_t c, int n) {
+  int t = __builtin_ctz(~c);
+  t = t < n ? t : n - 1;
+  return t < 0 ? 0u : tab[t];
 }
 
 // Offset change of a counter going from c to c + 1 when its bit i sits at
@@ -162,18 +185,6 @@ __device__ __forceinline__ uint32_t deposit_runs32(uint32_t v, const BitRuns& R)
 // work (two iterations on average).  Call only while c + 1 is in range.
 __device__ __forceinline__ uint64_t step_delta(uint64_t c, const int8_t* pos, int first) {
   const int t = __builtin_ctzll(~c);
-  uint64_t d = uint64_t(1) << pos_at(pos, first + t);
-  for (int b = 0; b < t; b++) d -= uint64_t(1) << pos_at(pos, first + b);
-  return d;
-}
-
-// The same for a counter of n bits, also callable at its last value (the
-// carry is clamped to the counter's width; the result is then not used), so
-// that walks need no guard around their loads.
-__device__ __forceinline__ uint64_t step_delta_n(uint64_t c, const int8_t* pos, int first, int n) {
-  int t = __builtin_ctzll(~c);
-  t = t < n ? t : n - 1;
-  if (t < 0) return 0;
   uint64_t d = uint64_t(1) << pos_at(pos, first + t);
   for (int b = 0; b < t; b++) d -= uint64_t(1) << pos_at(pos, first + b);
   return d;
@@ -208,7 +219,7 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
   const uint32_t oc = deposit_runs32(r32, op.run_c);
   uint32_t inb[NIN], inc[NIN];
 #pragma unroll
-  for (int j = 0; j < NIN; j++) { inb[j] = dep32(j, op.in_b, 0, op.n_in); inc[j] = dep32(j, op.in_c, 0, op.n_in); }
+  for (int j = 0; j < NIN; j++) { inb[j] = op.in_off_b[j]; inc[j] = op.in_off_c[j]; }
   V acc[NIN];
 #pragma unroll
   for (int j = 0; j < NIN; j++) { acc[j].x = 0; acc[j].y = 0; }
@@ -227,7 +238,7 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
       // k and k + 1 are adjacent in A: one 16-byte load for both; the counter
       // c runs over the summed bits above the lowest
       const uint32_t b1 = 1u << pos_at(op.k_b, 0);
-      uint32_t xa = 0, xb = 0, c = 0;
+      uint32_t xa = 0, xb = 0;
       for (uint32_t i = 0; i < (nk >> 1); i += U) {
         t4 a2[U];
         uint32_t bo[U];
@@ -235,9 +246,10 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
         for (int u = 0; u < U; u++) {
           a2[u] = *reinterpret_cast<GMEM const t4*>(A + oa + xa);
           bo[u] = ob + xb;
-          xa += (uint32_t)step_delta_n(c, op.k_a, 1, op.n_k - 1);
-          xb += (uint32_t)step_delta_n(c, op.k_b, 1, op.n_k - 1);
-          c++;
+          // i is a multiple of U: inside the chunk the carry position is static
+          const uint32_t c = u + 1 < U ? uint32_t(u) : i + u;
+          xa += kstep(op.kstep_a, c, op.n_k - 1);
+          xb += kstep(op.kstep_b, c, op.n_k - 1);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
         }
       }
     } else {
-      uint32_t xa = 0, xb = 0, c = 0;
+      uint32_t xa = 0, xb = 0;
       for (uint32_t i = 0; i < nk; i += U) {
         V a[U];
         uint32_t bo[U];
@@ -262,9 +274,9 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
         for (int u = 0; u < U; u++) {
           a[u] = conjv(ld(A + oa + xa), op.conj_a);
           bo[u] = ob + xb;
-          xa += (uint32_t)step_delta_n(c, op.k_a, 0, op.n_k);
-          xb += (uint32_t)step_delta_n(c, op.k_b, 0, op.n_k);
-          c++;
+          const uint32_t c = u + 1 < U ? uint32_t(u) : i + u;
+          xa += kstep(op.kstep_a, c, op.n_k);
+          xb += kstep(op.kstep_b, c, op.n_k);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -361,16 +373,18 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
   GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
   GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
   const int cbits = op.n_k - ks;                  // >= 6
-  const uint32_t ba = deposit_runs32(row, op.run_a) + dep32(chunk, op.k_a, cbits, ks) + dep32(lane, op.k_a, 0, 6);
-  const uint32_t bb = deposit_runs32(row, op.run_b) + dep32(chunk, op.k_b, cbits, ks) + dep32(lane, op.k_b, 0, 6);
+  const uint32_t ba = deposit_runs32(row, op.run_a) + deposit_runs32(chunk, op.run_ka_chunk) +
+                      deposit_runs32(lane, op.run_ka_lane);
+  const uint32_t bb = deposit_runs32(row, op.run_b) + deposit_runs32(chunk, op.run_kb_chunk) +
+                      deposit_runs32(lane, op.run_kb_lane);
   uint32_t inb[NIN];
 #pragma unroll
-  for (int j = 0; j < NIN; j++) inb[j] = dep32(j, op.in_b, 0, op.n_in);
+  for (int j = 0; j < NIN; j++) inb[j] = op.in_off_b[j];
   T ar[NIN], ai[NIN];
 #pragma unroll
   for (int j = 0; j < NIN; j++) { ar[j] = 0; ai[j] = 0; }
   const uint32_t steps = 1u << (cbits - 6);
-  uint32_t xa = 0, xb = 0, c = 0;
+  uint32_t xa = 0, xb = 0;
   for (uint32_t i = 0; i < steps; i += U) {
     V a[U];
     uint32_t bo[U];
@@ -378,9 +392,9 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
     for (int u = 0; u < U; u++) {
       a[u] = conjv(ld(A + ba + xa), op.conj_a);
       bo[u] = bb + xb;
-      xa += (uint32_t)step_delta_n(c, op.k_a, 6, cbits - 6);
-      xb += (uint32_t)step_delta_n(c, op.k_b, 6, cbits - 6);
-      c++;
+      const uint32_t c = u + 1 < U ? uint32_t(u) : i + u;
+      xa += kstep(op.kstep_a, c, cbits - 6);
+      xb += kstep(op.kstep_b, c, cbits - 6);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -400,7 +414,7 @@ __global__ __launch_bounds__(kRowThreads) void splitk_kernel(Ctx ctx, RowOp op) 
     const uint32_t oc = deposit_runs32(row, op.run_c);
 #pragma unroll
     for (int j = 0; j < NIN; j++) {
-      const uint32_t c = oc + dep32(j, op.in_c, 0, op.n_in);
+      const uint32_t c = oc + op.in_off_c[j];
       V o;
       o.x = ar[j];
       o.y = ai[j];
@@ -447,7 +461,7 @@ __global__ __launch_bounds__(kRowThreads) void reduce_kernel(Ctx ctx, RowOp op) 
   GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
   const uint64_t row = o >> op.n_in;
   const uint32_t j = (uint32_t)(o & ((1u << op.n_in) - 1));
-  const uint64_t c = deposit_runs(row, op.run_c) + deposit(j, op.in_c, 0, op.n_in);
+  const uint64_t c = deposit_runs(row, op.run_c) + op.in_off_c[j];
   V s;
   s.x = sx;
   s.y = sy;

@@ -74,6 +74,15 @@ struct RowOp {
   int8_t in_c[kMaxInThread], in_b[kMaxInThread];
   int8_t k_a[kMaxBits], k_b[kMaxBits];
   BitRuns run_a, run_b, run_c;   // row_a / row_b / row_c as runs
+  // Launch-time tables (prepare_row): offset of in-thread value j in B and
+  // in C, and the split-K lane bits (the six lowest summed bits) and chunk
+  // bits (the top k_split_bits) as runs in A and B.
+  uint32_t in_off_b[1 << kMaxInThread], in_off_c[1 << kMaxInThread];
+  BitRuns run_ka_lane, run_kb_lane, run_ka_chunk, run_kb_chunk;
+  // Offset change in A / B when the counter of the summed-bit walk carries
+  // into its bit t (the walk covers summed bits from the lowest, from the
+  // second for paired A loads, or from the seventh for split-K lanes).
+  uint32_t kstep_a[kMaxBits], kstep_b[kMaxBits];
 };
 
 // Matrix-core / tiled GEMM: C[h, m, n] = sum_k A[h, m, k] * opB(B[h, k, n]).
@@ -135,6 +144,53 @@ inline void make_runs(const int8_t* pos, int n, BitRuns& R) {
     R.r[R.n++] = uint32_t(i) | uint32_t(pos[i]) << 8 | uint32_t(len) << 16;
     i += len;
   }
+}
+
+// Launch-time tables of a row op, filled on the host from its position lists
+// (once per launch or graph capture): the row lists as runs, the in-thread
+// offsets, the split-K lane and chunk runs, and whether a wavefront's 64 rows
+// x in-thread values form one contiguous block of C (staged stores: no
+// split, no accumulation, the in-thread values at C's lowest positions and
+// the six lane bits of the row right above them).
+inline void prepare_row(RowOp& op) {
+  make_runs(op.row_a, op.n_rows, op.run_a);
+  make_runs(op.row_b, op.n_rows, op.run_b);
+  make_runs(op.row_c, op.n_rows, op.run_c);
+  for (int j = 0; j < (1 << kMaxInThread); j++) {
+    uint32_t ob = 0, oc = 0;
+    for (int i = 0; i < op.n_in; i++)
+      if ((j >> i) & 1) {
+        if (op.in_b[i] >= 0) ob |= 1u << op.in_b[i];
+        if (op.in_c[i] >= 0) oc |= 1u << op.in_c[i];
+      }
+    op.in_off_b[j] = ob;
+    op.in_off_c[j] = oc;
+  }
+  const int ks = op.k_split_bits > 0 ? op.k_split_bits : 0;
+  const int lane_bits = op.n_k < 6 ? op.n_k : 6;
+  make_runs(op.k_a, lane_bits, op.run_ka_lane);
+  make_runs(op.k_b, lane_bits, op.run_kb_lane);
+  make_runs(op.k_a + (op.n_k - ks), ks, op.run_ka_chunk);
+  make_runs(op.k_b + (op.n_k - ks), ks, op.run_kb_chunk);
+  const int first = op.k_split_bits >= 0 ? 6 : (op.pair_a ? 1 : 0);
+  const int walk = op.n_k - ks - first;
+  for (int t = 0; t < kMaxBits; t++) {
+    uint32_t da = 0, db = 0;
+    if (t < walk) {
+      da = 1u << op.k_a[first + t];
+      db = 1u << op.k_b[first + t];
+      for (int b = 0; b < t; b++) {
+        da -= 1u << op.k_a[first + b];
+        db -= 1u << op.k_b[first + b];
+      }
+    }
+    op.kstep_a[t] = da;
+    op.kstep_b[t] = db;
+  }
+  bool st = op.k_split_bits < 0 && op.pair_c && !op.accumulate && op.n_in >= 1 && op.n_rows >= 6;
+  for (int i = 0; st && i < op.n_in; i++) st = op.in_c[i] == i;
+  for (int i = 0; st && i < 6; i++) st = op.row_c[i] == op.n_in + i;
+  op.stage_c = st ? 1 : 0;
 }
 
 // Device code reads the int8 position lists a dword at a time: every op

@@ -64,13 +64,9 @@ static int chunk_bits(const RowOp& op) {
   return ub < kb ? ub : kb;
 }
 
-// the library's launcher picks the staged-store variant under these conditions
-static bool staged(const RowOp& op, int eb) {
-  bool st = eb == 8 && op.k_split_bits < 0 && op.pair_c && !op.accumulate && op.n_in >= 1 && op.n_rows >= 6;
-  for (int i = 0; st && i < op.n_in; i++) st = op.in_c[i] == i;
-  for (int i = 0; st && i < 6; i++) st = op.row_c[i] == op.n_in + i;
-  return st;
-}
+// the library's launcher picks the staged-store variant for complex64 ops
+// that prepare_row marks
+static bool staged(const RowOp& op, int eb) { return eb == 8 && op.stage_c; }
 
 template <typename T, int NIN, int U>
 static void call_row(bool stage, const Ctx& ctx, const RowOp& op) {
@@ -253,10 +249,8 @@ int main(int argc, char** argv) {
     *reinterpret_cast<int64_t*>(base + p->counter_off) = 0;
     *reinterpret_cast<int64_t*>(base + p->sid_off) = sid;
     for (const Op& op : p->fwd) {
-      RowOp r = op.row;                       // run tables, as the library's launchers fill them
-      make_runs(r.row_a, r.n_rows, r.run_a);
-      make_runs(r.row_b, r.n_rows, r.run_b);
-      make_runs(r.row_c, r.n_rows, r.run_c);
+      RowOp r = op.row;                       // launch-time tables, as the library's launchers fill them
+      prepare_row(r);
       if (op.kind == OpKind::RowReduce) {
         if (eb == 8) run_reduce<float>(ctx, r, 0); else run_reduce<double>(ctx, r, 0);
       } else if (r.k_split_bits >= 0) {
