@@ -234,8 +234,10 @@ __device__ __forceinline__ void gemm_store(const Ctx& ctx, const GemmOp& op, con
                          deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
-  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
-  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, 0, g.tn);
+  // tile-local offsets from the run tables (bits below tm / tn; deposits of
+  // disjoint bit sets add)
+  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit_runs(uint64_t(i), op.run_c_m);
+  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit_runs(uint64_t(i), op.run_c_n);
   __syncthreads();
   const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31, odd = c32 & 1;
   const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
@@ -578,8 +580,10 @@ __device__ __forceinline__ void gemm_store_3m(const Ctx& ctx, const GemmOp& op, 
                          deposit_runs(g.tile_n << g.tn, op.run_c_n);
   uint64_t* rowoff = tab;
   uint64_t* coloff = tab + BM;
-  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit(i, op.c_m, 0, g.tm);
-  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit(i, op.c_n, 0, g.tn);
+  // tile-local offsets from the run tables (bits below tm / tn; deposits of
+  // disjoint bit sets add)
+  for (int i = tid; i < BM; i += nthreads) rowoff[i] = deposit_runs(uint64_t(i), op.run_c_m);
+  for (int i = tid; i < BN; i += nthreads) coloff[i] = deposit_runs(uint64_t(i), op.run_c_n);
   __syncthreads();
   const int lane = tid & 63, hi = lane >> 5, c32 = lane & 31;
   const int mvalid = 1 << g.tm, nvalid = 1 << g.tn;
@@ -1110,11 +1114,11 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
   for (int i = 0; i < 4; i++) {
     const int row = ty + 16 * i;
     if (row >= mvalid) continue;
-    const uint64_t ro = deposit(row, op.c_m, 0, tm);
+    const uint64_t ro = deposit_runs(uint64_t(row), op.run_c_m);
     for (int j = 0; j < 4; j++) {
       const int col = tx + 16 * j;
       if (col >= nvalid) continue;
-      GMEM V* d = C + ro + deposit(col, op.c_n, 0, tn);
+      GMEM V* d = C + ro + deposit_runs(uint64_t(col), op.run_c_n);
       if (op.accumulate) { V o = ld(d); o.x += acc[i][j].x; o.y += acc[i][j].y; st(d, o); }
       else st(d, acc[i][j]);
     }

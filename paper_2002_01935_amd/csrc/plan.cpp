@@ -316,8 +316,22 @@ static int kernel_class(int prec, int m, int n, int k, int h) {
   (void)k;
   (void)h;
   (void)prec;
-  if (m >= 5 && n >= 5) return kGemm;
+  // an outer product (no summed bit) only writes its output, which the row
+  // kernel does in contiguous blocks; with summed bits a matrix-core tile
+  // reuses each B value across its rows, where the row kernel would reload it
+  if (m >= 5 && n >= 5 && k >= 1) return kGemm;
   return kRow;   // row or split-K, refined below
+}
+
+// Which operand supplies the in-thread (B) side of a node: for matrix-core
+// nodes and row nodes with two wide free sides, the side holding the
+// output's lowest axis (coalesced output tiles / contiguous row blocks);
+// otherwise the smaller free side.
+static bool pick_swap(int kc, const std::vector<int>& M, const std::vector<int>& N, const std::vector<int>& H,
+                      const std::vector<int>& cbits) {
+  const bool wide = kc == kGemm || ((int)M.size() > kMaxInThread && (int)N.size() > kMaxInThread);
+  if (wide) return !cbits.empty() && contains(M, cbits[0]) && !contains(H, cbits[0]);
+  return N.size() > M.size();
 }
 
 // Build one contraction op: C(out_bits in layout Cl) = sum A * op(B).
@@ -351,8 +365,7 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
   int kc = kernel_class(p->prec, m, n, k, h);
   bool swap = false;
   if (forced_swap >= 0) swap = forced_swap != 0;
-  else if (kc == kGemm) swap = !cb.empty() && contains(M, Cl.bits[0]) && !contains(H, Cl.bits[0]);
-  else swap = n > m;
+  else swap = pick_swap(kc, M, N, H, cb);
   const Operand& A = swap ? B0 : A0;
   const Operand& B = swap ? A0 : B0;
   int cA = swap ? conj_b : conj_a, cB = swap ? conj_a : conj_b;
@@ -399,18 +412,22 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     r.conj_a = cA;
     r.conj_b = cB;
     r.accumulate = accumulate ? 1 : 0;
+    // at most kMaxInThread free bits of B in each thread (those at C's
+    // lowest positions); the rest of B's free side joins the rows
+    const int nin = std::min(fb, kMaxInThread);
     std::vector<int> rows = H;
     rows.insert(rows.end(), FA.begin(), FA.end());
+    rows.insert(rows.end(), FB.begin() + nin, FB.end());
     byC(rows);
     r.n_rows = (int)rows.size();
-    r.n_in = fb;
+    r.n_in = nin;
     r.n_k = k;
     for (int i = 0; i < r.n_rows; i++) {
       r.row_c[i] = (int8_t)posC(rows[i]);
       r.row_a[i] = (int8_t)A.lay.pos_of(rows[i]);
       r.row_b[i] = (int8_t)B.lay.pos_of(rows[i]);
     }
-    for (int i = 0; i < fb; i++) { r.in_c[i] = (int8_t)posC(FB[i]); r.in_b[i] = (int8_t)B.lay.pos_of(FB[i]); }
+    for (int i = 0; i < nin; i++) { r.in_c[i] = (int8_t)posC(FB[i]); r.in_b[i] = (int8_t)B.lay.pos_of(FB[i]); }
     for (int i = 0; i < k; i++) { r.k_a[i] = (int8_t)A.lay.pos_of(K[i]); r.k_b[i] = (int8_t)B.lay.pos_of(K[i]); }
     // paired 16-byte accesses where the lowest bit of the run sits at
     // position 0 and no slice offset can make the base odd
@@ -420,7 +437,7 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
       return true;
     };
     r.pair_a = (k >= 1 && r.k_a[0] == 0 && even_base(r.a) && p->elem_bytes == 8) ? 1 : 0;
-    r.pair_c = (fb >= 1 && r.in_c[0] == 0 && even_base(r.c) && p->elem_bytes == 8) ? 1 : 0;
+    r.pair_c = (nin >= 1 && r.in_c[0] == 0 && even_base(r.c) && p->elem_bytes == 8) ? 1 : 0;
     // few rows and a long sum: lanes stride over K, chunks reduced in order
     int nrows = r.n_rows;
     if (nrows < 14 && k >= 6) {
@@ -429,7 +446,7 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
       r.k_split_bits = ks;
       op.grid_rows = int64_t(1) << (nrows + ks);
       if (ks > 0) {
-        int pb = prog.new_buf((int64_t)p->elem_bytes << (nrows + fb + ks));
+        int pb = prog.new_buf((int64_t)p->elem_bytes << (nrows + nin + ks));
         r.part = buf_ref(pb);
       }
     } else {
@@ -501,9 +518,7 @@ static void assign_layouts(tn_plan_s* p) {
     std::vector<int> H = ni.H, M = ni.M, N = ni.N, K = ni.K;
     byC(H); byC(M); byC(N);
     int kc = kernel_class(p->prec, (int)M.size(), (int)N.size(), (int)K.size(), (int)H.size());
-    bool swap;
-    if (kc == kGemm) swap = !Cl.bits.empty() && contains(M, Cl.bits[0]);
-    else swap = N.size() > M.size();
+    const bool swap = pick_swap(kc, M, N, H, Cl.bits);
     ni.kclass = kc;
     ni.swap = swap;
     int A = swap ? ni.r : ni.l, B = swap ? ni.l : ni.r;
