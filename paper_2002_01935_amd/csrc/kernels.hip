@@ -825,25 +825,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store_3m<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
-// bf16 round-to-nearest-even of a finite float, and back
-__device__ __forceinline__ uint32_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-__device__ __forceinline__ float bf16_f(uint32_t h) { return __uint_as_float(h << 16); }
-
 // BF16x3 on BF16 matrix cores: every FP32 operand x is split into
-// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32) and each real
-// product is formed as hi*hi + hi*lo + lo*hi with FP32 accumulation (the lo*lo
-// term, below 2^-16 relative, is dropped).  The complex product uses the same
-// real embedding as the 4M kernel; one v_mfma_f32_32x32x16_bf16 takes 8
-// complex k values (16 real) per lane pair of a 32 x 16 complex tile.  LDS
-// holds hi and lo of A and B as (re, im) bf16 pairs, k fastest; each lane
-// turns its B pairs into the (Br, -Bi) or (Bi, Br) pattern of its output
-// column parity.
-template <int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_mfma_bf16x3(Ctx ctx, GemmOp op) {
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32; both rounded to
+// nearest even by the hardware conversion) and each real product is formed as
+// hi*hi + hi*lo + lo*hi with FP32 accumulation (the lo*lo term, below 2^-16
+// relative, is dropped).  The complex product uses the same real embedding as
+// the 4M kernel; one v_mfma_f32_32x32x16_bf16 takes 8 complex k values (16
+// real) per lane pair of a 32 x 16 complex tile.  LDS holds hi and lo of A as
+// (re, im) bf16 pairs and of B in the two patterns the output column parity
+// needs, (Br, -Bi) and (Bi, Br), k fastest: formed once per element when the
+// stage is stored (negation and swap commute with the rounding), not at every
+// fragment read.
+template <int BM, int BN, int BK, int WGM, int WGN, int OCC = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_bf16x3(Ctx ctx, GemmOp op) {
   static_assert(((BK + 4) * 4) % 16 == 0, "fragment rows must stay 16-byte aligned");
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -852,7 +846,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = __builtin_ctz(BK);
   constexpr int LDK = BK + 4;                      // dwords per row: BK (re, im) pairs + pad (16-byte rows)
   static_assert(BK % 8 == 0, "BK must hold whole MFMA k steps");
-  __shared__ uint32_t lds[2][2][BM + BN][LDK];      // [buffer][hi/lo][A rows | B cols][k]
+  __shared__ uint32_t lds[2][2][BM + 2 * BN][LDK];  // [buffer][hi/lo][A rows | B cols even pattern | odd][k]
   static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
 
   GemmSetup g;
@@ -871,7 +865,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     tile_slots<LA, NT>(ma, tid, a_off, a_dst);
     tile_slots<LB, NT>(mb, tid, b_off, b_dst);
   }
-  for (int i = tid; i < 2 * 2 * (BM + BN) * LDK; i += NT) (&lds[0][0][0][0])[i] = 0u;
+  for (int i = tid; i < 2 * 2 * (BM + 2 * BN) * LDK; i += NT) (&lds[0][0][0][0])[i] = 0u;
   // k offsets of consecutive pipeline stages, advanced stage by stage with
   // the per-carry deltas of each operand (LDS table: no scalar loads, whose
   // completion wait would also drain the LDS reads in flight, in the loop)
@@ -899,11 +893,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     }
     kstep++;
   };
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
   auto split = [](float re, float im, uint32_t& h, uint32_t& l) {
-    const uint32_t hr = bf16_rne(re), hm = bf16_rne(im);
-    const uint32_t lr = bf16_rne(re - bf16_f(hr)), lm = bf16_rne(im - bf16_f(hm));
-    h = hr | (hm << 16);
-    l = lr | (lm << 16);
+    const bf2v hb = __builtin_convertvector(f2v{re, im}, bf2v);
+    const f2v back = __builtin_convertvector(hb, f2v);
+    const bf2v lb = __builtin_convertvector(f2v{re - back.x, im - back.y}, bf2v);
+    h = __builtin_bit_cast(uint32_t, hb);     // re in the low half
+    l = __builtin_bit_cast(uint32_t, lb);
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -921,8 +918,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
         const int col = b_dst[i] & (BN - 1), k = b_dst[i] >> RN;
         uint32_t h, l;
         split(rb[i].x, sb * rb[i].y, h, l);
-        lds[buf][0][BM + col][k] = h;
-        lds[buf][1][BM + col][k] = l;
+        // even output columns take (Br, -Bi): the sign of the high half
+        // flips; odd ones (Bi, Br): the halves swap
+        lds[buf][0][BM + col][k] = h ^ 0x80000000u;
+        lds[buf][1][BM + col][k] = l ^ 0x80000000u;
+        lds[buf][0][BM + BN + col][k] = (h >> 16) | (h << 16);
+        lds[buf][1][BM + BN + col][k] = (l >> 16) | (l << 16);
       }
   };
 
@@ -938,14 +939,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     for (int j = 0; j < FN; j++)
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-  // B pair (br, bi) -> (br, -bi) for even output columns, (bi, br) for odd;
-  // selected by mask, not by branch (the parity differs between lanes)
-  const uint32_t pmask = bpar ? 0xffffffffu : 0u;
-  auto bpat = [pmask](uint32_t d) {
-    const uint32_t sw = (d >> 16) | (d << 16), ng = d ^ 0x80000000u;
-    return (sw & pmask) | (ng & ~pmask);
-  };
-
   gload();
   sstore(0);
   __syncthreads();
@@ -964,15 +957,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       }
 #pragma unroll
       for (int j = 0; j < FN; j++) {
-        const int col = BM + wn * WN + j * 16 + (c32 >> 1);
-        const u32x4 h = *reinterpret_cast<const u32x4*>(&lds[buf][0][col][k0]);
-        const u32x4 l = *reinterpret_cast<const u32x4*>(&lds[buf][1][col][k0]);
-        u32x4 bh, bl;
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          bh[t] = bpat(h[t]);
-          bl[t] = bpat(l[t]);
-        }
+        // the pattern of this lane's output column parity
+        const int col = BM + bpar * BN + wn * WN + j * 16 + (c32 >> 1);
+        const u32x4 bh = *reinterpret_cast<const u32x4*>(&lds[buf][0][col][k0]);
+        const u32x4 bl = *reinterpret_cast<const u32x4*>(&lds[buf][1][col][k0]);
         // hi*hi, hi*lo, lo*hi, interleaved over the row fragments so that no
         // two consecutive matrix-core ops write the same accumulator
 #pragma unroll
@@ -1314,9 +1302,10 @@ static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec,
   if (prec == TN_C64_BF16X3) {
     switch (tile) {
       case 0: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
-      case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2>), grid, dim3(128), 0, s, ctx, op); break;
+      // the 64-row variants load twice as many elements per thread: one wave per SIMD
+      case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
       case 2: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 64, 8, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
-      case 3: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 64, 8, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
+      case 3: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 64, 8, 1, 1, 1>), grid, dim3(64), 0, s, ctx, op); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
