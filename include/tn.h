@@ -137,15 +137,20 @@ int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t*
 
 /*
  * Optional autotune pass: times the candidate tile shapes of every distinct
- * matrix-core contraction shape on synthetic data in `workspace` and keeps the
- * fastest in the plan.  Overwrites the workspace; synchronises the stream.
+ * matrix-core contraction shape of the forward program on synthetic data in
+ * `workspace` and keeps the fastest in the plan, for the forward and the
+ * backward program (contractions of the same shape, split and operand
+ * layout class).  Without it, a contraction takes the direct-to-LDS variant
+ * where its operands allow (tile 9 for TN_C64_4M, 7 for TN_C64_3M), else
+ * tile 0.  Clears a tile pinned by tn_plan_set_tile.  Overwrites the
+ * workspace; synchronises the stream.
  */
 int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void* stream);
 
 /*
  * Pin the tile variant of every matrix-core contraction of the plan (forward
- * and backward programs) that variant `tile` can run, in place of the default
- * or autotuned choice; the others keep theirs.  Variants: 0 = 128x128,
+ * and backward programs, also one built later) that variant `tile` can run,
+ * in place of the default or autotuned choice; the others keep theirs.  Variants: 0 = 128x128,
  * 1 = 64x128, 2 = 128x64, 3 = 64x64 (every precision); 4 = vector ALU; for
  * TN_C64_4M also 5 = 256x128 and 6 = 128x128 with raised matrix-core
  * priority; for TN_C64_4M and TN_C64_3M 7 = 128x128, 8 = 256x128 and

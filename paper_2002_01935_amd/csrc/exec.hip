@@ -41,6 +41,8 @@ static int set_err(int code, const std::string& msg) {
 
 extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
 
+static void assign_tiles(tn_plan_s* p, std::vector<Op>& prog);
+
 extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* leaf_idx, int32_t n_idx,
                        const int64_t* idx_dim, int32_t n_out, const int64_t* out_idx, const int32_t* left,
                        const int32_t* right, int32_t n_sliced, const int64_t* sliced_idx,
@@ -85,6 +87,7 @@ extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* lea
     delete p;
     return set_err(rc, err);
   }
+  assign_tiles(p, p->fwd);
   *plan = p;
   return TN_OK;
 }
@@ -101,6 +104,28 @@ extern "C" int tn_plan_info(tn_plan_t p, int32_t* W, int32_t* W_s, double* log2_
   return TN_OK;
 }
 
+// Tile variant of every matrix-core contraction of a program: the pinned
+// variant where it applies, else the autotuned one of its shape, else the
+// direct-to-LDS variant where the operands allow it (4M at three waves per
+// SIMD, 3M with 64 x 64 waves), else the register-staged 128 x 128 tile.
+static std::array<int, 6> tile_key(const GemmOp& g, int prec) {
+  return {g.n_h, g.n_m, g.n_n, g.n_k, g.k_split_bits, gemm_tile_ok(g, 7, prec) ? 1 : 0};
+}
+
+static void assign_tiles(tn_plan_s* p, std::vector<Op>& prog) {
+  for (Op& op : prog) {
+    if (op.kind != OpKind::Gemm) continue;
+    GemmOp& g = op.gemm;
+    int t = 0;
+    auto it = p->tile_choice.find(tile_key(g, p->prec));
+    if (p->pinned_tile >= 0 && gemm_tile_ok(g, p->pinned_tile, p->prec)) t = p->pinned_tile;
+    else if (it != p->tile_choice.end()) t = it->second;
+    else if (p->prec == TN_C64_4M && gemm_tile_ok(g, 9, p->prec)) t = 9;
+    else if (p->prec == TN_C64_3M && gemm_tile_ok(g, 7, p->prec)) t = 7;
+    g.tile = gemm_tile_ok(g, t, p->prec) ? t : 0;
+  }
+}
+
 static int ensure_backward(tn_plan_s* p, int32_t n_wrt, const int32_t* wrt) {
   if (n_wrt < 0 || (n_wrt > 0 && !wrt)) return set_err(TN_E_INVALID, "null wrt list");
   std::vector<int32_t> w(wrt, wrt + n_wrt);
@@ -108,6 +133,7 @@ static int ensure_backward(tn_plan_s* p, int32_t n_wrt, const int32_t* wrt) {
   std::string err;
   int rc = build_backward(p, w, err);
   if (rc) return set_err(rc, err);
+  assign_tiles(p, p->bwd);
   // the cached backward graphs belong to the previous wrt set
   for (auto it = p->graphs.begin(); it != p->graphs.end();) {
     if (it->first.first == 2) {
@@ -532,15 +558,13 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  struct Key { int h, m, n, k; bool operator<(const Key& o) const { return std::tie(h, m, n, k) < std::tie(o.h, o.m, o.n, o.k); } };
-  std::map<Key, int> best;
+  std::map<std::array<int, 6>, int> best;
   for (Op& op : p->fwd) {
     if (op.kind != OpKind::Gemm) continue;
     GemmOp& g = op.gemm;
     if (g.a.kind != 1 || g.b.kind != 1) continue;   // leaf operands: keep the default
-    Key key{g.n_h, g.n_m, g.n_n, g.n_k};
-    auto it = best.find(key);
-    if (it != best.end()) { g.tile = it->second; continue; }
+    const std::array<int, 6> key = tile_key(g, p->prec);
+    if (best.count(key)) continue;
     float best_ms = 1e30f;
     int best_tile = 0;
     // matrix-core tiles only; the summed range is cut to at most 2^9 values
@@ -565,11 +589,14 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
                 ms / reps, trial.n_k);
       if (ms < best_ms) { best_ms = ms; best_tile = t; }
     }
-    g.tile = best_tile;
     best[key] = best_tile;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  p->tile_choice = best;
+  p->pinned_tile = -1;
+  assign_tiles(p, p->fwd);
+  if (p->bwd_built) assign_tiles(p, p->bwd);
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
   p->graphs.clear();
   p->tuned = true;
@@ -581,6 +608,7 @@ extern "C" int tn_plan_set_tile(tn_plan_t p, int32_t tile, int32_t* n_set) {
   int bm, bn;
   if (gemm_tile_bits(tile, &bm, &bn)) return set_err(TN_E_INVALID, "unknown tile variant");
   int32_t n = 0;
+  p->pinned_tile = tile;                 // also for a backward program built later
   for (auto* prog : {&p->fwd, &p->bwd})
     for (Op& op : *prog)
       if (op.kind == OpKind::Gemm && op.gemm.tile != tile && gemm_tile_ok(op.gemm, tile, p->prec)) {

@@ -1,6 +1,7 @@
 // Host-side plan: everything tn_plan fixes once per network structure and tree.
 #pragma once
 
+#include <array>
 #include <cstring>
 #include <map>
 #include <string>
@@ -106,6 +107,11 @@ struct tn_plan_s {
   // cached HIP graphs, keyed by (mode, workspace address)
   std::map<std::pair<int, uint64_t>, void*> graphs;
   bool tuned = false;
+  // matrix-core tile variants: autotuned choice per (h, m, n, k, split bits,
+  // direct-to-LDS eligible), applied to the forward and backward programs;
+  // a variant pinned by tn_plan_set_tile (-1: none) goes wherever it applies
+  std::map<std::array<int, 6>, int> tile_choice;
+  int pinned_tile = -1;
 };
 
 namespace tn {

@@ -174,6 +174,7 @@ def test_backward_direct_to_lds(oracle_lib, prec):
         for t in (7, 8, 9):
             plan = _plan(net, two, precision=prec)
             plan.backward_info([0, 1])
+            plan.set_tile(0)           # off the direct-to-LDS default, so that pinning t changes the op
             changed = plan.set_tile(t)
             note("backward dl", prec, case, "tile", t, "changed", changed)
             assert changed >= 1

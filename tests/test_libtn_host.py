@@ -138,7 +138,8 @@ def test_set_tile(B):
     assert p.set_tile(0) == 1
     p3 = B.Plan(net, two, precision="c64_3m")
     assert p3.set_tile(5) == 0         # 4M-only variant
-    assert p3.set_tile(7) == 1         # 3M direct-to-LDS variant
+    assert p3.set_tile(7) == 0         # 3M direct-to-LDS: already the default
+    assert p3.set_tile(9) == 1
     assert p3.set_tile(1) == 1
     q = B.Plan(_canonical_pair(7, 7, 5, k_first=True), two, precision="c64_4m")
     assert q.set_tile(8) == 0          # summed bits not lowest in A
