@@ -222,3 +222,30 @@ def test_gemm_split_k(oracle_lib, prec):
     ref = oracle_lib.contract(net, TWO, sliced=sl)
     note("split-k sliced", prec)
     assert rel(gpu_sliced(net, TWO, sliced=sl, precision=prec, max_inflight=2), ref) < TOLS[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128", "c64_3m", "c64_bf16x3"])
+def test_degenerate_networks(oracle_lib, prec):
+    """A single leaf (the result is the leaf permuted to the output order), an
+    index of dimension 1 between two leaves (an outer product in disguise),
+    a scalar from two vectors, and a network whose only summed index has
+    dimension 1 next to a real contraction."""
+    one = Tree(np.zeros(0, np.int32), np.zeros(0, np.int32))
+    rng = np.random.default_rng(11)
+
+    def cn(*shape):
+        return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+    cases = [
+        (Network([cn(2, 4, 2)], [[0, 1, 2]], [2, 4, 2], [2, 0, 1]), one),
+        (Network([cn(8, 1), cn(1, 4)], [[0, 1], [1, 2]], [8, 1, 4], [0, 2]), TWO),
+        (Network([cn(64), cn(64)], [[0], [0]], [64], []), TWO),
+        (Network([cn(2, 1, 16), cn(16, 1, 4)], [[0, 1, 2], [2, 3, 4]], [2, 1, 16, 1, 4], [0, 1, 3, 4]), TWO),
+    ]
+    for i, (net, tree) in enumerate(cases):
+        note("degenerate", prec, i)
+        ref = oracle_lib.contract(net, tree)
+        got = gpu_sliced(net, tree, precision=prec)
+        assert got.shape == ref.shape, i
+        assert rel(got, ref) < TOLS[prec], i
+        assert rel(gpu_contract(net, tree, precision=prec), ref) < TOLS[prec], i

@@ -162,3 +162,38 @@ def test_split_k_gemm_plan(B):
     assert [n["kclass"] for n in B.Plan(_canonical_pair(10, 10, 14), two).nodes()] == ["gemm_splitk"]   # 64 tiles
     assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 14), two).nodes()] == ["gemm"]
     assert [n["kclass"] for n in B.Plan(pairwise_network(0, 8, 7, 11, seed=1), two).nodes()] == ["gemm_splitk"]
+
+
+def test_size_limits(B):
+    # tensors of 2^32 or more elements after slicing are rejected (32-bit
+    # offsets in the bandwidth kernels); slicing brings the same network in
+    # range.  Zero-stride views stand in for the leaves: the planner reads
+    # shapes only.
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+
+    def big(shape):
+        return np.broadcast_to(np.zeros(1, np.complex128), shape)
+
+    outer = Network([big((2,) * 17), big((2,) * 17)], [list(range(17)), list(range(17, 34))], [2] * 34,
+                    list(range(34)))
+    with pytest.raises(B.TNError) as e:
+        B.Plan(outer, two)
+    assert e.value.code == -2
+    wide = Network([big((2,) * 33), big((2,) * 3)], [list(range(33)), [0, 1, 2]], [2] * 33, list(range(3, 33)))
+    with pytest.raises(B.TNError) as e:
+        B.Plan(wide, two)
+    assert e.value.code == -2
+    p = B.Plan(wide, two, sliced=[1, 2])
+    assert p.info()["d_sliced"] == 4 and p.info()["W_s"] == 31
+
+
+def test_degenerate_plans(B):
+    # a single leaf (no contraction: a permutation to the output order) and
+    # an index of dimension 1 (no bits) are valid networks
+    one = Tree(np.zeros(0, np.int32), np.zeros(0, np.int32))
+    single = Network([np.zeros((2, 4, 2), complex)], [[0, 1, 2]], [2, 4, 2], [2, 0, 1])
+    p = B.Plan(single, one)
+    assert p.out_shape == (2, 2, 4) and p.info()["flops_per_slice"] == 0
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    unit = Network([np.ones((2, 1)), np.ones((1, 2))], [[0, 1], [1, 2]], [2, 1, 2], [0, 2])
+    assert [n["logK"] for n in B.Plan(unit, two).nodes()] == [0]
