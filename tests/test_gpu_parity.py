@@ -249,3 +249,36 @@ def test_degenerate_networks(oracle_lib, prec):
         assert got.shape == ref.shape, i
         assert rel(got, ref) < TOLS[prec], i
         assert rel(gpu_contract(net, tree, precision=prec), ref) < TOLS[prec], i
+
+
+def test_graph_replays_match_eager(oracle_lib, monkeypatch):
+    """The sliced contraction replays one captured HIP graph per batch of
+    in-flight slices.  Several calls, each replaying the graph more than once,
+    with unrelated eager PyTorch work and synchronisations in between, give
+    bitwise the result of the same kernels launched eagerly (TN_NO_GRAPH=1):
+    a hyperedge circuit (row, split-K row and GEMM kernels, reductions) and a
+    split-K GEMM node (partial tiles and their fixed-order sum)."""
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    circ = circuit_network(4, 5, 12, 5, 0b1011001110100101, open_qubits=(2, 9, 13), decompose="swap_diag")
+    ctree = find_tree(circ, seed=0, trials=4, slice_width=16)
+    pair = pairwise_network(0, 8, 7, 12, seed=40, dims=(2,))
+    pk = [e for e in range(pair.n_idx) if e not in pair.out_idx]
+    cases = [(circ, ctree, list(ctree.meta["sliced"])), (pair, TWO, pk[:2])]
+    x = torch.randn(512, 512, device="cuda")
+    for ci, (net, tree, sl) in enumerate(cases):
+        ids = list(range(0, 2 ** len(sl), 3)) if len(sl) > 2 else list(range(2 ** len(sl)))
+        ref = oracle_lib.contract(net, tree, sliced=sl, slice_ids=ids)
+        monkeypatch.setenv("TN_NO_GRAPH", "1")
+        eager = gpu_sliced(net, tree, sliced=sl, slice_ids=ids, precision="c64_4m", max_inflight=2)
+        monkeypatch.delenv("TN_NO_GRAPH")
+        assert rel(eager, ref) < TOL_C64, ci
+        plan = Plan(net, tree, sliced=sl, precision="c64_4m", max_inflight_slices=2)
+        for r in range(4):
+            note("graph replay", ci, "call", r)
+            got = gpu_sliced(net, tree, sliced=sl, slice_ids=ids, plan=plan)
+            assert np.array_equal(got, eager), (ci, r)
+            y = (x @ x).sum()                      # eager work between the calls
+            torch.cuda.synchronize()
+            assert torch.isfinite(y)
