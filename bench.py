@@ -376,7 +376,49 @@ def node_bench(spec, precision, reps):
                       "gbs": round(best["bytes"] / best["ms"] / 1e6, 1), "ms_per_tile": per_tile, "reps": reps}))
 
 
+def sampling_bench(n_samples):
+    """Sampling driver (Sec. 4.7.3) on a 6x6 grid circuit, 12 cycles, with the
+    central 2x3 block of qubits open (64 amplitudes per contraction): samples
+    from psi at fidelity 1, one sliced contraction each (tree sliced to width
+    28); prints the time per contraction and the projected time of 10^6
+    samples at f = 0.002 (f M contractions)."""
+    import numpy as np
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    from paper_2002_01935_amd.sampling import CircuitSampler
+    from tn_inputs.circuits import circuit_network, gate_leaves
+    from tn_inputs.greedy import find_tree
+    R, C, m = 6, 6, 12
+    opened = (14, 15, 16, 20, 21, 22)
+    net = circuit_network(R, C, m, 0, 0, open_qubits=opened)
+    tree = find_tree(net, seed=0, trials=8, slice_width=28)
+    plan = Plan(net, tree, sliced=tree.meta["sliced"], precision="c64_4m")
+    ws = plan.workspace()
+    plan.tune(ws)
+    leaves = [torch.from_numpy(np.ascontiguousarray(t)).to("cuda", plan.storage_dtype) for t in net.leaves]
+    closed = [q for q in range(R * C) if q not in opened]
+    sampler = CircuitSampler(plan, leaves, R * C, closed, opened, gate_leaves(net, "out"), workspace=ws)
+    sampler.conditional(0)                    # first call captures the graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    samples, nc = sampler.sample(n_samples, 1.0, np.random.default_rng(0))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = plan.info()
+    per = el / max(nc, 1)
+    print(json.dumps({"mode": "sample", "workload": "6x6 grid circuit, 12 cycles, qubits 14-16 and 20-22 open, "
+                      "sliced to W_s=28", "W": info["W"], "W_s": info["W_s"], "d_sliced": info["d_sliced"],
+                      "contractions": nc, "s_per_contraction": round(per, 4),
+                      "tflops": round(info["flops_per_slice"] * info["d_sliced"] / per / 1e12, 2),
+                      "projected_s_1e6_samples_f0.002": round(1e6 * 0.002 * per, 1),
+                      "samples": [format(b, "09x") for b in samples]}))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--sample":
+        sampling_bench(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+        return
     if len(sys.argv) > 2 and sys.argv[1] == "--node":
         prec = sys.argv[3] if len(sys.argv) > 3 else "c64_4m"
         node_bench(sys.argv[2], prec, int(sys.argv[4]) if len(sys.argv) > 4 else 3)
