@@ -415,7 +415,62 @@ def sampling_bench(n_samples):
                       "samples": [format(b, "09x") for b in samples]}))
 
 
+def qaoa_bench(n, p, n_streams):
+    """QAOA MAX-CUT energy (Sec. 4.4) on a seeded random 3-regular graph: one
+    light-cone network per edge, each with its own tree and plan (complex64
+    4M), contracted back to back on one stream and round-robin over
+    `n_streams` streams (default priority, one workspace per plan); the many
+    small networks make it launch-latency bound."""
+    import numpy as np
+    import torch
+
+    from paper_2002_01935_amd.binding import Plan
+    from tn_inputs.greedy import find_tree
+    from tn_inputs.qaoa import instance, term_network
+    edges, gammas, betas = instance(n, p, 0)
+    t0 = time.perf_counter()
+    plans, leaves, wss, outs = [], [], [], []
+    flops = 0.0
+    for j, k in edges:
+        net = term_network(edges, gammas, betas, j, k)
+        tree = find_tree(net, seed=0, trials=4)
+        pl = Plan(net, tree, precision="c64_4m")
+        flops += pl.info()["flops_per_slice"]
+        plans.append(pl)
+        leaves.append([torch.from_numpy(np.ascontiguousarray(t)).to("cuda", pl.storage_dtype) for t in net.leaves])
+        wss.append(pl.workspace())
+        outs.append(torch.empty((), dtype=torch.complex64, device="cuda"))
+    t_plan = time.perf_counter() - t0
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+
+    def run(concurrent):
+        for i, pl in enumerate(plans):
+            s = streams[i % n_streams] if concurrent else torch.cuda.current_stream()
+            with torch.cuda.stream(s):
+                pl.contract(leaves[i], out=outs[i], workspace=wss[i], stream=s)
+        torch.cuda.synchronize()
+
+    res = {}
+    for name, conc in (("one_stream", False), (f"{n_streams}_streams", True)):
+        run(conc)                                  # captures the graphs
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            run(conc)
+            ts.append(time.perf_counter() - t1)
+        res[name + "_s"] = round(sorted(ts)[1], 5)
+    energy = float(sum(complex(o.item()).real for o in outs))
+    print(json.dumps({"mode": "qaoa", "workload": f"MAX-CUT QAOA, random 3-regular graph N={n}, p={p}, seed 0",
+                      "terms": len(plans), "leaves_per_term_max": max(len(l) for l in leaves),
+                      "flops_8C_total": flops, "plan_s": round(t_plan, 2), **res,
+                      "tflops_best": round(flops / min(res.values()) / 1e12, 4), "energy": energy}))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--qaoa":
+        a = sys.argv[2:]
+        qaoa_bench(int(a[0]) if a else 54, int(a[1]) if len(a) > 1 else 3, int(a[2]) if len(a) > 2 else 8)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--sample":
         sampling_bench(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
         return

@@ -83,8 +83,10 @@ def _arr(a, dtype):
 
 
 def _stream(stream):
+    """A torch.cuda.Stream, a raw hipStream_t handle (int), or None for the
+    current stream."""
     if stream is not None:
-        return ctypes.c_void_p(stream)
+        return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
