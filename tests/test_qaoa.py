@@ -73,3 +73,22 @@ def test_terms_gpu_vs_oracle(oracle_lib, n, p, seed):
         e64.append(g64.real)
     assert abs(sum(e128) - ref_sv.sum()) < 1e-9
     assert abs(sum(e64) - ref_sv.sum()) < 1e-4
+
+
+@pytest.mark.gpu
+def test_full_size_instance_vs_oracle(oracle_lib):
+    """The measured instance (N = 54, p = 3, 81 terms): every term's complex64
+    value against the oracle's complex128 contraction of the same network
+    and tree, and the energy sum."""
+    from tests.gpu_util import gpu_contract, note
+    edges, gammas, betas = instance(54, 3, 0)
+    ref, got = [], []
+    for i, (j, k) in enumerate(edges):
+        net = term_network(edges, gammas, betas, j, k)
+        tree = find_tree(net, seed=0, trials=4)
+        if i % 20 == 0:
+            note("qaoa full size term", i)
+        ref.append(complex(oracle_lib.contract(net, tree)).real)
+        got.append(complex(gpu_contract(net, tree, precision="c64_4m")).real)
+    assert np.max(np.abs(np.array(got) - np.array(ref))) < 1e-5
+    assert abs(sum(got) - sum(ref)) < 1e-4
