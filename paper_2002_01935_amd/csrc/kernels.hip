@@ -835,7 +835,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 // (re, im) bf16 pairs and of B in the two patterns the output column parity
 // needs, (Br, -Bi) and (Bi, Br), k fastest: formed once per element when the
 // stage is stored (negation and swap commute with the rounding), not at every
-// fragment read.
+// fragment read.  The two patterns of a B column sit in adjacent rows, so the
+// 16 lanes of a fragment read (8 columns x 2 parities) hit 16 consecutive
+// rows, whose 128-bit pieces fall in disjoint banks.
 template <int BM, int BN, int BK, int WGM, int WGN, int OCC = 2>
 __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_bf16x3(Ctx ctx, GemmOp op) {
   static_assert(((BK + 4) * 4) % 16 == 0, "fragment rows must stay 16-byte aligned");
@@ -846,7 +848,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = __builtin_ctz(BK);
   constexpr int LDK = BK + 4;                      // dwords per row: BK (re, im) pairs + pad (16-byte rows)
   static_assert(BK % 8 == 0, "BK must hold whole MFMA k steps");
-  __shared__ uint32_t lds[2][2][BM + 2 * BN][LDK];  // [buffer][hi/lo][A rows | B cols even pattern | odd][k]
+  __shared__ uint32_t lds[2][2][BM + 2 * BN][LDK];  // [buffer][hi/lo][A rows | B col 0 even, odd pattern, col 1 ...][k]
   static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
 
   GemmSetup g;
@@ -920,10 +922,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
         split(rb[i].x, sb * rb[i].y, h, l);
         // even output columns take (Br, -Bi): the sign of the high half
         // flips; odd ones (Bi, Br): the halves swap
-        lds[buf][0][BM + col][k] = h ^ 0x80000000u;
-        lds[buf][1][BM + col][k] = l ^ 0x80000000u;
-        lds[buf][0][BM + BN + col][k] = (h >> 16) | (h << 16);
-        lds[buf][1][BM + BN + col][k] = (l >> 16) | (l << 16);
+        lds[buf][0][BM + 2 * col][k] = h ^ 0x80000000u;
+        lds[buf][1][BM + 2 * col][k] = l ^ 0x80000000u;
+        lds[buf][0][BM + 2 * col + 1][k] = (h >> 16) | (h << 16);
+        lds[buf][1][BM + 2 * col + 1][k] = (l >> 16) | (l << 16);
       }
   };
 
@@ -958,7 +960,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int j = 0; j < FN; j++) {
         // the pattern of this lane's output column parity
-        const int col = BM + bpar * BN + wn * WN + j * 16 + (c32 >> 1);
+        const int col = BM + 2 * (wn * WN + j * 16 + (c32 >> 1)) + bpar;
         const u32x4 bh = *reinterpret_cast<const u32x4*>(&lds[buf][0][col][k0]);
         const u32x4 bl = *reinterpret_cast<const u32x4*>(&lds[buf][1][col][k0]);
         // hi*hi, hi*lo, lo*hi, interleaved over the row fragments so that no
