@@ -9,7 +9,7 @@ is cancellation-heavy; BF16x3 within its stated bound."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import TOL_BF16X3, TOL_C64, note, project, rel, sub_slice_id, to_dev
+from tests.gpu_util import TOL_3M, TOL_BF16X3, TOL_C64, note, project, rel, sub_slice_id, to_dev
 from tn_inputs import configs
 from tn_inputs.slicing import extend_slices
 
@@ -40,12 +40,14 @@ def _run(name, prec, log2_target, slice_pos, seed_vals, oracle_lib):
     return err, net, tree, ext, sid
 
 
-@pytest.mark.parametrize("prec", ["c64_4m", "c64_bf16x3"])
+@pytest.mark.parametrize("prec", ["c64_4m", "c64_bf16x3", "c64_3m"])
 def test_cfg5_full_slice(oracle_lib, prec):
     err, net, tree, ext, sid = _run("cfg5", prec, 33.0, 7, 1, oracle_lib)
     note("cfg5", prec, "rel err", err)
     if prec == "c64_bf16x3":
         assert err < TOL_BF16X3
+    elif prec == "c64_3m" and err <= TOL_3M:
+        pass
     elif err > TOL_C64:
         kappa = oracle_lib.root_condition(net, tree, ext, slice_ids=[sid])
         note("cfg5 kappa", kappa, "backward", err / kappa)
