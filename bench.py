@@ -594,6 +594,21 @@ def main():
                "sample": f"one sub-slice of the same tree with {len(ext) - len(sliced)} extra sliced indices "
                          f"(8C = {8 * 2 ** lc:.3e} complex FLOPs) in {tc:.1f} s, complex128 loop nest"}
         log(f"cpu oracle: {cpu['value'] * 1e3:.3f} GFLOP/s on {threads} threads ({tc:.1f} s)")
+        # the same oracle on one thread, on a sub-slice with a few more sliced indices
+        ext1 = extend_slices(net, tree, sliced, target - 4.0)
+        _, lc1 = oc.width_cost(net, tree, sliced=ext1)
+        t0 = time.perf_counter()
+        oc.contract(net, tree, sliced=ext1, slice_ids=[0], n_threads=1)
+        tc1 = time.perf_counter() - t0
+        cpu["single_thread"] = {"value": round(8 * 2 ** lc1 / tc1 / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
+                                "sample": f"one sub-slice with {len(ext1) - len(sliced)} extra sliced indices "
+                                          f"(8C = {8 * 2 ** lc1:.3e}) in {tc1:.1f} s"}
+        log(f"cpu oracle: {cpu['single_thread']['value'] * 1e3:.3f} GFLOP/s on 1 thread ({tc1:.1f} s)")
+        try:
+            cpu["cpu_model"] = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                                    if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
 
     plain = None
     plain_ref = None

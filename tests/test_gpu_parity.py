@@ -161,6 +161,40 @@ def test_cfg2_rrg(oracle_lib, seed):
     assert err3 <= TOL_3M or err3 / kappa <= TOL_C64
 
 
+def test_cfg2_error_study(oracle_lib):
+    """The 120-vertex random 3-regular network over seeds 0-9: relative error
+    of every precision against the oracle's complex128 value, with
+    kappa = ||T_l|| ||T_r|| / |Z| of the root's children.  Each single
+    precision passes on its relative bound or, for a cancellation-heavy
+    scalar, on the normwise backward error err / kappa within the same
+    bound (4M and 3M: 1e-5; BF16x3: its own bound).  Prints the median and
+    maximum per precision."""
+    errs = {p: [] for p in ("c128", "c64_4m", "c64_3m", "c64_bf16x3")}
+    kappas = []
+    bounds = {"c64_4m": (TOL_C64, TOL_C64), "c64_3m": (TOL_3M, TOL_C64), "c64_bf16x3": (TOL_BF16X3, TOL_BF16X3)}
+    for seed in range(10):
+        net = rrg_network(120, 3, seed=seed)
+        tree = find_tree(net, seed=seed, trials=8, slice_width=20)
+        sl = tree.meta["sliced"]
+        ref = complex(oracle_lib.contract(net, tree, sliced=sl))
+        kappa = oracle_lib.root_condition(net, tree, sl)
+        kappas.append(kappa)
+        for prec in errs:
+            got = complex(gpu_sliced(net, tree, sliced=sl, precision=prec))
+            err = abs(got - ref) / abs(ref)
+            errs[prec].append(err)
+            note("cfg2 study seed", seed, prec, "rel err", err, "kappa", kappa)
+            if prec == "c128":
+                assert err <= TOL_C128
+            else:
+                rel_bound, back_bound = bounds[prec]
+                assert err <= rel_bound or err / kappa <= back_bound, (seed, prec, err, kappa)
+    note("cfg2 study kappa median", float(np.median(kappas)), "max", max(kappas))
+    for prec, e in errs.items():
+        back = [x / k for x, k in zip(e, kappas)]
+        note("cfg2 study", prec, "rel err median", float(np.median(e)), "max", max(e), "backward max", max(back))
+
+
 def test_sliced_subsets_and_batches(oracle_lib):
     net = random_network(10, 16, 4, seed=7, n_out=1, dims=(2,), hyper=False)
     tree = find_tree(net, seed=1, trials=2)
