@@ -174,7 +174,11 @@ int tn_contract(tn_plan_t plan, const void* const* leaves, void* out,
  * Sliced contraction (Sec. 4.7.1): the sum over the given slice ids of the
  * contraction with the sliced indices fixed to each id's values.
  * n_ids, slice_ids  host array of ids in [0, d_sliced); NULL = every id in
- *                   ascending order.  Ids are summed in the order given.
+ *                   ascending order.  Ids are summed in the order given.  The
+ *                   workspace holds the id list: one call takes at most
+ *                   max(d_sliced, slices per graph replay) ids, capped at 2^22
+ *                   (NULL with d_sliced above the cap is refused too); longer
+ *                   lists return TN_E_INVALID; sum them over several calls.
  * out_c128          device pointer, complex128, out_idx order; overwritten with
  *                   the FP64 sum (each slice's root is promoted to FP64 and added
  *                   in a fixed order, so repeated calls are bitwise identical)

@@ -105,6 +105,45 @@ def test_workspace_and_null_checks(B):
     assert b"null" in B.lib.tn_last_error()
 
 
+def test_slice_id_and_wrt_errors(B):
+    """Argument errors of the contraction calls are reported before any device
+    work (placeholder device pointers are never dereferenced): slice ids
+    outside [0, d_sliced), a negative count, the unsliced entry point on a
+    sliced plan, and wrt leaves out of range or listed twice."""
+    net = random_network(6, 8, 4, seed=1)
+    net = Network(net.leaves, net.leaf_idx, [2] * net.n_idx, net.out_idx)
+    tree = find_tree(net, seed=0, trials=1)
+    inner = next(e for e in range(net.n_idx) if e not in net.out_idx)
+    p = B.Plan(net, tree, sliced=[inner])
+    assert p.info()["d_sliced"] == 2
+    need = p.info()["workspace_bytes"]
+    dev = ctypes.c_void_p(0x1000)
+    dummy = (ctypes.c_void_p * net.n_leaves)(*([0x1000] * net.n_leaves))
+
+    def sliced(ids, n=None):
+        arr = np.array(ids, dtype=np.int64)
+        return B.lib.tn_contract_sliced(p.handle, dummy, len(ids) if n is None else n,
+                                        arr.ctypes.data_as(ctypes.c_void_p), dev, dev, need, None)
+
+    for ids in ([2], [1, 2], [-1]):
+        assert sliced(ids) == -1
+        assert b"out of range" in B.lib.tn_last_error()
+    assert sliced([0, 1, 0]) == -1           # more ids than one call batches
+    assert b"too many" in B.lib.tn_last_error()
+    assert sliced([0], n=-1) == -1
+    assert b"negative" in B.lib.tn_last_error()
+    assert B.lib.tn_contract(p.handle, dummy, dev, dev, need, None) == -1
+    assert b"sliced" in B.lib.tn_last_error()
+
+    grads = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    for wrt, msg in (([net.n_leaves], b"out of range"), ([-1], b"out of range"), ([0, 0], b"twice")):
+        w = np.array(wrt, dtype=np.int32)
+        rc = B.lib.tn_contract_backward(p.handle, dummy, dev, len(wrt), w.ctypes.data_as(ctypes.c_void_p), grads,
+                                        0, None, dev, 1 << 40, None)
+        assert rc == -1
+        assert msg in B.lib.tn_last_error()
+
+
 def test_backward_plan_recomputes(B):
     # the reverse program keeps few large intermediates: its workspace stays
     # far below the sum of every node value, and its FLOPs include recomputation
