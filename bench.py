@@ -16,9 +16,14 @@ Printed as one JSON line:
               with HIP events around every launch over the same number of
               steps, against the FP32 matrix-core peak (157.3 TFLOP/s)
   cpu_baseline  the CPU oracle on one sub-slice of the same tree (more
-              indices sliced so that it runs in seconds), same FLOP convention
+              indices sliced so that it runs in seconds), same FLOP convention,
+              on all host threads and on one
   plain_fp64  the same tree and slice run node by node with materialised
               permutes and complex128 matmuls in PyTorch (one slice)
+  variants    the same slices with 3M and BF16x3, each with its dominant
+              launch's rate in the FLOPs its matrix cores execute
+  adjoint     forward and reverse pass on cfg4 (all 180 fSim leaf gradients),
+              with the oracle's forward and gradient of one sub-slice beside it
 """
 
 from __future__ import annotations
@@ -288,12 +293,15 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 4, "dispatches": 3}))
 
 
-def adjoint_bench(precision, torch, np, Plan, configs, reps=3):
+def adjoint_bench(precision, torch, np, Plan, configs, reps=3, cpu_threads=0):
     """Reverse mode on cfg4 (6x6 grid, 12 cycles, width 28): the amplitude c,
     then dL/dconj(G) of L = |c|^2 for all 180 fSim leaves through
     tn_contract_backward (recomputation from checkpoints).  Times are medians of
     `reps` warm calls; FLOPs are the planner's 8C counts of the forward and of
-    the backward program (recomputation included)."""
+    the backward program (recomputation included).  With `cpu_threads`, the
+    complex128 oracle's forward and gradient of one sub-slice (8 more sliced
+    indices) are timed too, and scaled by the number of sub-slices to the
+    whole gradient (an extrapolation: every sub-slice has the same cost)."""
     from tn_inputs.circuits import gate_leaves
     net, tree, sliced = configs.load("cfg4")
     plan = Plan(net, tree, sliced=sliced, precision=precision)
@@ -320,10 +328,27 @@ def adjoint_bench(precision, torch, np, Plan, configs, reps=3):
     f_fl = plan.info()["flops_per_slice"] * plan.info()["d_sliced"]
     b_fl = binfo["flops_per_slice"] * plan.info()["d_sliced"]
     tfm, tbm = sorted(tf)[len(tf) // 2], sorted(tb)[len(tb) // 2]
-    return {"workload": "cfg4: 6x6 grid circuit, 12 cycles, one amplitude, W=28; d|amp|^2/d(all 180 fSim leaves)",
-            "precision": precision, "forward_s": round(tfm, 4), "backward_s": round(tbm, 4),
-            "forward_tflops": round(f_fl / tfm / 1e12, 2), "backward_tflops": round(b_fl / tbm / 1e12, 2),
-            "backward_over_forward_flops": round(b_fl / f_fl, 2), "n_grads": len(wrt)}
+    res = {"workload": "cfg4: 6x6 grid circuit, 12 cycles, one amplitude, W=28; d|amp|^2/d(all 180 fSim leaves)",
+           "precision": precision, "forward_s": round(tfm, 4), "backward_s": round(tbm, 4),
+           "forward_tflops": round(f_fl / tfm / 1e12, 2), "backward_tflops": round(b_fl / tbm / 1e12, 2),
+           "backward_over_forward_flops": round(b_fl / f_fl, 2), "n_grads": len(wrt)}
+    if cpu_threads:
+        from oracle import contract as oc
+        from tn_inputs.slicing import extend_slices
+        ext = extend_slices(net, tree, sliced, 33.0)
+        _, lc = oc.width_cost(net, tree, sliced=ext)
+        t0 = time.perf_counter()
+        oc.contract(net, tree, sliced=ext, slice_ids=[0], n_threads=cpu_threads)
+        t1 = time.perf_counter()
+        oc.grad(net, tree, np.array(1.0 + 0j), wrt, sliced=ext, slice_ids=[0], n_threads=cpu_threads)
+        t2 = time.perf_counter()
+        n_sub = 2 ** len(ext)
+        res["cpu_oracle"] = {
+            "kind": "oracle", "cores": cpu_threads, "forward_s": round(t1 - t0, 2), "gradient_s": round(t2 - t1, 2),
+            "sample": f"one sub-slice of {n_sub} ({len(ext) - len(sliced)} extra sliced indices, forward "
+                      f"8C = {8 * 2 ** lc:.3e}), complex128",
+            "extrapolated_forward_plus_gradient_s": round((t2 - t0) * n_sub, 1)}
+    return res
 
 
 def node_bench(spec, precision, reps):
@@ -604,6 +629,7 @@ def main():
                                 "sample": f"one sub-slice with {len(ext1) - len(sliced)} extra sliced indices "
                                           f"(8C = {8 * 2 ** lc1:.3e}) in {tc1:.1f} s"}
         log(f"cpu oracle: {cpu['single_thread']['value'] * 1e3:.3f} GFLOP/s on 1 thread ({tc1:.1f} s)")
+        cpu["host_cpus"] = os.cpu_count()
         try:
             cpu["cpu_model"] = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
                                     if ln.startswith("model name"))
@@ -666,7 +692,9 @@ def main():
         except NameError:
             pass
         torch.cuda.empty_cache()
-        adjoint = adjoint_bench(args.precision, torch, np, Plan, configs)
+        adjoint = adjoint_bench(args.precision, torch, np, Plan, configs,
+                                cpu_threads=0 if args.no_cpu_baseline else
+                                int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
         log(f"adjoint (cfg4): {adjoint}")
 
     res = {
