@@ -22,6 +22,7 @@
 
 #include "kernels.h"
 #include "plan.h"
+#include "smallk.h"
 
 using namespace tn;
 
@@ -198,7 +199,8 @@ static hipError_t launch_op(const tn_plan_s* p, const Ctx& ctx, const Op& op, hi
   switch (op.kind) {
     case OpKind::Row: return launch_row(ctx, op.row, f64, s);
     case OpKind::RowReduce: return launch_reduce(ctx, op.row, f64, s);
-    case OpKind::Gemm: return launch_gemm(ctx, op.gemm, p->prec, s);
+    case OpKind::Gemm:
+      return gemm_smallk_ok(op.gemm) ? launch_gemm_smallk(ctx, op.gemm, p->prec, s) : launch_gemm(ctx, op.gemm, p->prec, s);
     case OpKind::Accum: return launch_accum(ctx, op.accum, f64, s);
     case OpKind::Permute: return launch_permute(ctx, op.perm, f64, s);
     case OpKind::Fill: return hipSuccess;
@@ -563,6 +565,7 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     if (op.kind != OpKind::Gemm) continue;
     GemmOp& g = op.gemm;
     if (g.a.kind != 1 || g.b.kind != 1) continue;   // leaf operands: keep the default
+    if (gemm_smallk_ok(g)) continue;                // few summed values: no tile to choose
     const std::array<int, 6> key = tile_key(g, p->prec);
     if (best.count(key)) continue;
     float best_ms = 1e30f;
