@@ -316,10 +316,12 @@ static int kernel_class(int prec, int m, int n, int k, int h) {
   (void)k;
   (void)h;
   (void)prec;
-  // an outer product (no summed bit) only writes its output, which the row
-  // kernel does in contiguous blocks; with summed bits a matrix-core tile
-  // reuses each B value across its rows, where the row kernel would reload it
-  if (m >= 5 && n >= 5 && k >= 1) return kGemm;
+  // two wide free sides: a GEMM op.  With many summed values a matrix-core
+  // tile reuses each B value across its rows, where the row kernel would
+  // reload it; with at most four (an outer product included) the product is
+  // bound by the write of C and runs on the few-summed-values kernel, whose
+  // threads keep their own operand values in registers across 16 rows
+  if (m >= 5 && n >= 5) return kGemm;
   return kRow;   // row or split-K, refined below
 }
 
