@@ -1,4 +1,5 @@
-// Host build of the row / split-K / reduce kernels (csrc/rowops.h) with
+// Host build of the row / split-K / reduce kernels (csrc/rowops.h) and of the
+// few-summed-values GEMM kernel (csrc/smallk_kernel.h) with
 // stand-ins for the HIP names they use, driven by the real planner
 // (csrc/plan.cpp): plans a network read from a text file, runs the forward
 // program's ops on the CPU (one host thread per lane for split-K wavefronts,
@@ -10,6 +11,7 @@
 //            n_sliced sliced... / n_ids ids...
 //   LEAVES.bin: complex128 leaves, row-major; OUT.bin: complex128 roots (out order), one per id
 // exit code 3: the plan holds an op kind the emulator does not run (matrix-core GEMM)
+// exit code 4: a few-summed-values GEMM op its launch preparation refused
 #include <barrier>
 #include <cstdint>
 #include <cstdio>
@@ -22,6 +24,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "smallk_rule.h"
 
 struct float2 { float x, y; };
 struct double2 { double x, y; };
@@ -51,6 +54,7 @@ static T __shfl_xor(T v, int mask, int) {
 
 namespace tn {
 #include "rowops.h"
+#include "smallk_kernel.h"
 }
 using namespace tn;
 
@@ -170,6 +174,38 @@ static void run_reduce(const Ctx& ctx, const RowOp& op, int z) {
   for (auto& t : lanes) t.join();
 }
 
+// One launch of the few-summed-values GEMM kernel: every (block, thread) in
+// turn (the kernel has no cross-lane step).
+template <typename T, bool FASTN, int P>
+static void run_smallk_variant(const Ctx& ctx, const GemmOp& op, const SmallkTables& kt, const SmallkLaunch& L) {
+  blockDim = {256, 1, 1};
+  for (uint64_t y = 0; y < L.gy; y++)
+    for (uint64_t x = 0; x < L.blocks; x++)
+      for (unsigned t = 0; t < 256; t++) {
+        blockIdx = {(unsigned)x, (unsigned)y, 0};
+        threadIdx = {t, 0, 0};
+        gemm_smallk<T, FASTN, P, kSmallkRows>(ctx, op, kt);
+      }
+}
+
+static bool run_smallk(const Ctx& ctx, const GemmOp& in, int prec) {
+  GemmOp op = in;
+  SmallkTables kt;
+  SmallkLaunch L;
+  if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return false;
+  if (prec == TN_C128) {
+    if (L.fastn) run_smallk_variant<double, true, 1>(ctx, op, kt, L);
+    else run_smallk_variant<double, false, 1>(ctx, op, kt, L);
+  } else if (L.pair) {
+    if (L.fastn) run_smallk_variant<float, true, 2>(ctx, op, kt, L);
+    else run_smallk_variant<float, false, 2>(ctx, op, kt, L);
+  } else {
+    if (L.fastn) run_smallk_variant<float, true, 1>(ctx, op, kt, L);
+    else run_smallk_variant<float, false, 1>(ctx, op, kt, L);
+  }
+  return true;
+}
+
 int main(int argc, char** argv) {
   if (argc != 4) return 1;
   FILE* f = fopen(argv[1], "r");
@@ -202,7 +238,8 @@ int main(int argc, char** argv) {
   std::string err;
   if (build_plan(p, err)) { fprintf(stderr, "plan: %s\n", err.c_str()); return 2; }
   for (const Op& op : p->fwd)
-    if (op.kind != OpKind::Row && op.kind != OpKind::RowReduce) return 3;
+    if (op.kind != OpKind::Row && op.kind != OpKind::RowReduce && !(op.kind == OpKind::Gemm && gemm_smallk_ok(op.gemm)))
+      return 3;
   const int eb = p->elem_bytes;
   // leaves, each in its own exactly sized buffer
   std::vector<std::vector<char>> leaves(nl);
@@ -249,6 +286,10 @@ int main(int argc, char** argv) {
     *reinterpret_cast<int64_t*>(base + p->counter_off) = 0;
     *reinterpret_cast<int64_t*>(base + p->sid_off) = sid;
     for (const Op& op : p->fwd) {
+      if (op.kind == OpKind::Gemm) {
+        if (!run_smallk(ctx, op.gemm, prec)) return 4;
+        continue;
+      }
       RowOp r = op.row;                       // launch-time tables, as the library's launchers fill them
       prepare_row(r);
       if (op.kind == OpKind::RowReduce) {

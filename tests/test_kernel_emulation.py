@@ -1,5 +1,5 @@
-"""The bandwidth-class kernels (row, split-K and its reduction: csrc/rowops.h)
-compiled for the host with stand-ins for the HIP names they use and run on
+"""The bandwidth-class kernels (row, split-K and its reduction: csrc/rowops.h;
+the few-summed-values GEMM: csrc/smallk_kernel.h) compiled for the host with stand-ins for the HIP names they use and run on
 the CPU by tests/emu/emu_rowops.cpp, driven by the real planner, against the
 oracle.  This checks their operand addressing (bit-permuted layouts, paired
 accesses, summed-index walks whose order differs between the operands,
@@ -78,6 +78,25 @@ def test_pairwise_emulated(emu, oracle_lib, tmp_path, shape, prec):
         net = pairwise_network(*shape, seed=1000 + 17 * seed + sum(shape), dims=(2, 4))
         got = run(emu, net, prec, tmp=str(tmp_path))
         assert got is not None, "plan uses a matrix-core GEMM; pick a smaller free side"
+        ref = oracle_lib.contract(net, TWO).ravel()
+        assert rel(got, ref) < TOL[prec], (shape, prec, seed)
+
+
+# (h, m, n, k): GEMM-class contractions with at most two summed bits (outer
+# products included), which take the few-summed-values kernel
+SMALLK = [(0, 5, 5, 1), (2, 6, 5, 2), (1, 5, 7, 0), (0, 7, 5, 2), (3, 5, 5, 1), (0, 6, 6, 0)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK)
+def test_smallk_emulated(emu, oracle_lib, tmp_path, shape, prec):
+    """gemm_smallk on the host (csrc/smallk_kernel.h) with random axis orders:
+    either free side may hold C's lowest bit, with and without the paired
+    16-byte stores, batch bits and conjugation-free operands."""
+    for seed in range(3):
+        net = pairwise_network(*shape, seed=2000 + 31 * seed + sum(shape), dims=(2, 4))
+        got = run(emu, net, prec, tmp=str(tmp_path))
+        assert got is not None, "plan uses a matrix-core GEMM"
         ref = oracle_lib.contract(net, TWO).ravel()
         assert rel(got, ref) < TOL[prec], (shape, prec, seed)
 
