@@ -6,7 +6,7 @@
 
 typedef float smallk_f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSmallkRows = 16;   // rows of the shared index per thread
+constexpr int kSmallkRows = 32;   // rows of the shared index per thread
 
 // Offsets the host computes once per launch: of summed value k in the
 // thread's own operand (kf) and in the shared one (ks); of row i < R of the
@@ -14,7 +14,7 @@ constexpr int kSmallkRows = 16;   // rows of the shared index per thread
 // the thread's first row (a multiple of R, so the bit sets are disjoint);
 // of the thread's second own index (P = 2) in its operand (f1).
 struct SmallkTables {
-  uint32_t kf[4], ks[4], si[16], ci[16], f1;
+  uint32_t kf[4], ks[4], si[32], ci[32], f1;
 };
 
 template <typename T, bool FASTN, int P, int R>
