@@ -601,7 +601,13 @@ def main():
         if 0 <= dom["node"] - net.n_leaves < len(nodes):
             nd = nodes[dom["node"] - net.n_leaves]
             roof["log2_hmnk"] = [nd["logH"], nd["logM"], nd["logN"], nd["logK"]]
-            roof["traffic"] = measured_traffic(KERNEL[args.precision], args.precision, args.workload, roof["log2_hmnk"])
+            # the kernel and tile that ran, and the autotune trials of its shape
+            roof["kernel"] = nd["kernel"]
+            roof["tile"] = nd["tile"]
+            shape = roof["log2_hmnk"]
+            roof["autotune"] = [{"tile": t["tile"], "k_bits": t["k_bits"], "median_ms": round(t["ms"], 3)}
+                                for t in plan.tune_trials() if t["shape"][:4] == shape]
+            roof["traffic"] = measured_traffic(nd["kernel"], args.precision, args.workload, roof["log2_hmnk"])
         log(f"dominant gemm node {dom['node']}: {avg_s * 1e3:.2f} ms/launch, {achieved:.1f} TFLOP/s")
 
     cpu = None
@@ -645,8 +651,21 @@ def main():
             err = float(np.linalg.norm(plan1 - ref) / np.linalg.norm(ref))
             plain = {"s_per_slice": round(tp, 4), "speedup": round(tp / per_slice, 2),
                      "rel_err_vs_fp64_plain": err}
-            log(f"plain fp64 path: {tp:.2f} s/slice, speedup {tp / per_slice:.1f}x, rel err {err:.2e}")
-            plain_ref = ref
+            if args.precision != "c128":
+                # the same FP64 path on the complex64-rounded leaves the plan
+                # receives: the contraction's own error, without the inputs'
+                net64 = net.with_leaves([np.asarray(t).astype(np.complex64).astype(np.complex128)
+                                         for t in net.leaves])
+                ref64, _ = plain_fp64(net64, tree, sliced, ids_all[0], torch)
+                plain["rel_err_vs_fp64_plain_same_leaves"] = float(np.linalg.norm(plan1 - ref64)
+                                                                   / np.linalg.norm(ref64))
+                plain["max_componentwise_err_same_leaves"] = float(np.abs(plan1 - ref64).max()
+                                                                   / np.abs(ref64).max())
+                plain["input_rounding_rel"] = float(np.linalg.norm(ref64 - ref) / np.linalg.norm(ref))
+                plain_ref = ref64
+            else:
+                plain_ref = ref
+            log(f"plain fp64 path: {tp:.2f} s/slice, speedup {tp / per_slice:.1f}x, {plain}")
         except torch.cuda.OutOfMemoryError as e:   # the plain path materialises every permute
             plain = {"error": f"out of memory: {e}"[:200]}
         torch.cuda.empty_cache()
@@ -673,13 +692,15 @@ def main():
             _, vops = vp.contract_sliced_timed(leaves, slice_ids=step_ids(args.warmup), out=out, workspace=vws)
             vg = max((o for o in vops if o["kind"] == "gemm"), key=lambda o: o["ms"])
             vt = vg["flops"] * EXECUTED[prec] / (vg["ms"] / 1e3 / B) / 1e12
-            rec["roofline"] = {"bound": "mfma", "kernel": KERNEL[prec], "node": vg["node"],
+            vnd = vp.nodes()[vg["node"] - net.n_leaves]
+            rec["roofline"] = {"bound": "mfma", "kernel": vnd["kernel"], "tile": vnd["tile"], "node": vg["node"],
                                "achieved": round(vt, 2), "peak": PEAK[prec], "unit": "TFLOP/s",
                                "frac": round(vt / PEAK[prec], 4), "executed_per_8C": EXECUTED[prec],
                                "avg_launch_ms": round(vg["ms"] / B, 3)}
             if plain_ref is not None:
                 v1 = vp.contract_sliced(leaves, slice_ids=[ids_all[0]], out=out, workspace=vws).cpu().numpy()
-                rec["rel_err_vs_fp64_plain"] = float(np.linalg.norm(v1 - plain_ref) / np.linalg.norm(plain_ref))
+                rec["rel_err_vs_fp64_plain_same_leaves"] = float(np.linalg.norm(v1 - plain_ref)
+                                                                 / np.linalg.norm(plain_ref))
             variants[prec] = rec
             log(f"variant {prec}: {rec}")
             del vws, vp

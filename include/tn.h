@@ -26,8 +26,15 @@
  *     it owns are HIP graphs cached inside a plan.  All work is enqueued on
  *     the caller's stream (a hipStream_t passed as void*; NULL = default
  *     stream); calls return without waiting for the GPU.
- *   - One plan may be used by several threads only with distinct workspaces.
- *     Calls that share a workspace must be ordered on one stream.
+ *   - Threads: every entry point that takes a plan holds that plan's lock
+ *     while it reads or changes the plan's mutable state (cached graphs, the
+ *     reverse program, tile choices) and enqueues its work, so several host
+ *     threads may call into one plan at once.  Calls that run at the same
+ *     time on the GPU must use distinct workspaces; calls that share a
+ *     workspace must be ordered, e.g. on one stream.  A plan caches at most 8 graphs,
+ *     one per (call kind, workspace address); the least recently used one is
+ *     freed, after its last launch has finished, when a ninth is needed.
+ *     tn_plan_destroy must not race with other calls on the same plan.
  */
 #ifndef TN_H
 #define TN_H
@@ -139,7 +146,9 @@ int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t*
 /*
  * Optional autotune pass: times the candidate tile shapes of every distinct
  * matrix-core contraction shape of the forward program on synthetic data in
- * `workspace` and keeps the fastest in the plan, for the forward and the
+ * `workspace` (summed range cut to at most 2^12 values per split; one warm-up
+ * launch, then the median of three timed launches; tn_plan_tune_trials
+ * reports the table) and keeps the fastest in the plan, for the forward and the
  * backward program (contractions of the same shape, split and operand
  * layout class).  Without it, a contraction takes the direct-to-LDS variant
  * where its operands allow (tile 9 for TN_C64_4M, 7 for TN_C64_3M), else
@@ -222,6 +231,26 @@ int tn_contract_sliced_timed(tn_plan_t plan, const void* const* leaves, int64_t 
                              uint64_t workspace_bytes, void* stream, int32_t cap, float* op_ms,
                              int32_t* op_kind, int32_t* op_node, double* op_flops,
                              double* op_bytes, int32_t* n_ops);
+
+/*
+ * Kernel of internal node k's contraction in the forward program, for
+ * reporting: *tile receives the matrix-core tile variant (-1 for vector-ALU
+ * kernels; 4 for complex128 products), `name` (capacity name_cap bytes, NUL
+ * terminated, truncated if short) the kernel's name with its template
+ * arguments, e.g. "gemm_mfma_4m_dl<128,128,2,2,3>".  Either may be NULL.
+ * TN_E_INVALID for k outside [0, number of internal nodes).  Host-only.
+ */
+int tn_plan_node_kernel(tn_plan_t plan, int32_t k, int32_t* tile, char* name, int32_t name_cap);
+
+/*
+ * Trials of the last tn_plan_tune: *n receives their number; for i < min(*n,
+ * cap): keys[6i .. 6i+5] the contraction shape (log2 H, M, N, K, split bits,
+ * 1 if both operands hold the summed indices lowest), tiles[i] the variant,
+ * k_bits[i] log2 of the summed range it ran with, ms[i] its median time.
+ * Output arrays may be NULL.  Host-only.
+ */
+int tn_plan_tune_trials(tn_plan_t plan, int32_t cap, int32_t* n, int32_t* keys, int32_t* tiles,
+                        int32_t* k_bits, float* ms);
 
 void tn_plan_destroy(tn_plan_t plan);
 

@@ -27,7 +27,8 @@ KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm", 3: "gemm_splitk"}
 EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
-    "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile",
+    "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile", "tn_plan_node_kernel",
+    "tn_plan_tune_trials",
 ]
 OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
 
@@ -60,6 +61,8 @@ def _load():
     lib.tn_contract_sliced.argtypes = [P, P, i64, P, P, P, u64, P]
     lib.tn_contract_backward.argtypes = [P, P, P, i32, P, P, i64, P, P, u64, P]
     lib.tn_contract_sliced_timed.argtypes = [P, P, i64, P, P, P, u64, P, i32, P, P, P, P, P, P]
+    lib.tn_plan_node_kernel.argtypes = [P, i32, P, ctypes.c_char_p, i32]
+    lib.tn_plan_tune_trials.argtypes = [P, i32, P, P, P, P, P]
     lib.tn_plan_destroy.argtypes = [P]
     lib.tn_plan_destroy.restype = None
     lib.tn_last_error.restype = ctypes.c_char_p
@@ -89,6 +92,18 @@ def _stream(stream):
         return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _on_stream(stream, make):
+    """Run `make()` (a torch allocation) with `stream` current, so that the
+    caching allocator ties the new tensor to the stream the library enqueues
+    its work on; None = the current stream."""
+    if stream is None or not hasattr(stream, "cuda_stream"):
+        if stream is not None:
+            raise ValueError("pass a torch.cuda.Stream, or preallocate every buffer for a raw stream handle")
+        return make()
+    with torch.cuda.stream(stream):
+        return make()
 
 
 def _dev_ptrs(tensors):
@@ -161,8 +176,28 @@ class Plan:
             vals = [ctypes.c_int32() for _ in range(5)] + [ctypes.c_double(), ctypes.c_double()]
             _check(lib.tn_plan_node_info(self.handle, k, *[ctypes.byref(v) for v in vals]))
             kc, h, m, nn, kk, fl, by = [v.value for v in vals]
-            out.append(dict(kclass=KERNEL_CLASSES[kc], logH=h, logM=m, logN=nn, logK=kk, flops=fl, bytes=by))
+            tile = ctypes.c_int32()
+            name = ctypes.create_string_buffer(96)
+            _check(lib.tn_plan_node_kernel(self.handle, k, ctypes.byref(tile), name, len(name)))
+            out.append(dict(kclass=KERNEL_CLASSES[kc], logH=h, logM=m, logN=nn, logK=kk, flops=fl, bytes=by,
+                            tile=tile.value, kernel=name.value.decode()))
         return out
+
+    def tune_trials(self) -> list:
+        """Autotune trials of the last tune(): shape (h, m, n, k, split bits,
+        direct-to-LDS eligible), tile, log2 of the trial's summed range and
+        the median time in ms."""
+        n = ctypes.c_int32()
+        _check(lib.tn_plan_tune_trials(self.handle, 0, ctypes.byref(n), None, None, None, None))
+        cap = n.value
+        keys = np.zeros(6 * max(cap, 1), np.int32)
+        tiles = np.zeros(max(cap, 1), np.int32)
+        kb = np.zeros(max(cap, 1), np.int32)
+        ms = np.zeros(max(cap, 1), np.float32)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib.tn_plan_tune_trials(self.handle, cap, ctypes.byref(n), vp(keys), vp(tiles), vp(kb), vp(ms)))
+        return [dict(shape=[int(x) for x in keys[6 * i:6 * i + 6]], tile=int(tiles[i]), k_bits=int(kb[i]),
+                     ms=float(ms[i])) for i in range(min(cap, n.value))]
 
     # ---------------------------------------------------------------- device calls
 
@@ -177,10 +212,9 @@ class Plan:
                 raise ValueError(f"leaf {v} has shape {tuple(t.shape)}, expected {self.leaf_shapes[v]}")
         return torch
 
-    def workspace(self, nbytes=None):
-        import torch
+    def workspace(self, nbytes=None, stream=None):
         n = self.info()["workspace_bytes"] if nbytes is None else int(nbytes)
-        return torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        return _on_stream(stream, lambda: torch.empty(max(n, 1), dtype=torch.uint8, device="cuda"))
 
     def tune(self, workspace, stream=None):
         _check(lib.tn_plan_tune(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
@@ -196,9 +230,9 @@ class Plan:
     def contract(self, leaves, out=None, workspace=None, stream=None):
         torch = self._check_leaves(leaves)
         if out is None:
-            out = torch.empty(self.out_shape, dtype=self.storage_dtype, device="cuda")
+            out = _on_stream(stream, lambda: torch.empty(self.out_shape, dtype=self.storage_dtype, device="cuda"))
         if workspace is None:
-            workspace = self.workspace()
+            workspace = self.workspace(stream=stream)
         _check(lib.tn_contract(self.handle, _dev_ptrs(leaves), ctypes.c_void_p(out.data_ptr()),
                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
         return out
@@ -206,11 +240,11 @@ class Plan:
     def contract_sliced(self, leaves, slice_ids=None, out=None, workspace=None, stream=None):
         torch = self._check_leaves(leaves)
         if out is None:
-            out = torch.empty(self.out_shape, dtype=torch.complex128, device="cuda")
+            out = _on_stream(stream, lambda: torch.empty(self.out_shape, dtype=torch.complex128, device="cuda"))
         if out.dtype != torch.complex128 or not out.is_contiguous():
             raise ValueError("out must be a contiguous complex128 CUDA tensor")
         if workspace is None:
-            workspace = self.workspace()
+            workspace = self.workspace(stream=stream)
         if slice_ids is None:
             n, ptr, keep = 0, None, None
         else:
@@ -225,9 +259,9 @@ class Plan:
         returns (out, [dict(kind, node, ms, flops, bytes) per op])."""
         torch = self._check_leaves(leaves)
         if out is None:
-            out = torch.empty(self.out_shape, dtype=torch.complex128, device="cuda")
+            out = _on_stream(stream, lambda: torch.empty(self.out_shape, dtype=torch.complex128, device="cuda"))
         if workspace is None:
-            workspace = self.workspace()
+            workspace = self.workspace(stream=stream)
         if slice_ids is None:
             n, ptr, keep = 0, None, None
         else:
@@ -252,10 +286,11 @@ class Plan:
         torch = self._check_leaves(leaves)
         wrt = [int(v) for v in wrt]
         if grads is None:
-            grads = [torch.empty(self.leaf_shapes[v], dtype=self.storage_dtype, device="cuda") for v in wrt]
-        go = grad_out.to(device="cuda", dtype=torch.complex128).contiguous()
+            grads = _on_stream(stream, lambda: [torch.empty(self.leaf_shapes[v], dtype=self.storage_dtype,
+                                                            device="cuda") for v in wrt])
+        go = _on_stream(stream, lambda: grad_out.to(device="cuda", dtype=torch.complex128).contiguous())
         if workspace is None:
-            workspace = self.workspace(self.backward_info(wrt)["workspace_bytes"])
+            workspace = self.workspace(self.backward_info(wrt)["workspace_bytes"], stream=stream)
         w, wp = _arr(wrt, np.int32)
         if slice_ids is None:
             n, ptr, keep = 0, None, None

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,30 @@ static int set_err(int code, const std::string& msg) {
   } while (0)
 
 extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
+
+using PlanLock = std::lock_guard<std::mutex>;
+
+// Wait for the last launch of a cached graph, then free it.
+static void destroy_graph(tn_plan_s::GraphEntry& e) {
+  if (e.done) {
+    (void)hipEventSynchronize((hipEvent_t)e.done);
+    (void)hipEventDestroy((hipEvent_t)e.done);
+  }
+  if (e.exec) (void)hipGraphExecDestroy((hipGraphExec_t)e.exec);
+  e = tn_plan_s::GraphEntry{};
+}
+
+// Drop the cached graphs of one mode (-1: every mode).
+static void drop_graphs(tn_plan_s* p, int mode) {
+  for (auto it = p->graphs.begin(); it != p->graphs.end();) {
+    if (mode < 0 || it->first.first == mode) {
+      destroy_graph(it->second);
+      it = p->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
 
 static void assign_tiles(tn_plan_s* p, std::vector<Op>& prog);
 
@@ -96,6 +121,7 @@ extern "C" int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* lea
 extern "C" int tn_plan_info(tn_plan_t p, int32_t* W, int32_t* W_s, double* log2_C, double* flops_8C_per_slice,
                             int64_t* d_sliced, uint64_t* workspace_bytes) {
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (W) *W = p->W;
   if (W_s) *W_s = p->W_s;
   if (log2_C) *log2_C = p->log2_C;
@@ -136,20 +162,14 @@ static int ensure_backward(tn_plan_s* p, int32_t n_wrt, const int32_t* wrt) {
   if (rc) return set_err(rc, err);
   assign_tiles(p, p->bwd);
   // the cached backward graphs belong to the previous wrt set
-  for (auto it = p->graphs.begin(); it != p->graphs.end();) {
-    if (it->first.first == 2) {
-      (void)hipGraphExecDestroy((hipGraphExec_t)it->second);
-      it = p->graphs.erase(it);
-    } else {
-      ++it;
-    }
-  }
+  drop_graphs(p, 2);
   return TN_OK;
 }
 
 extern "C" int tn_plan_backward_info(tn_plan_t p, int32_t n_wrt, const int32_t* wrt, uint64_t* workspace_bytes,
                                      double* flops_per_slice) {
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   int rc = ensure_backward(p, n_wrt, wrt);
   if (rc) return rc;
   if (workspace_bytes) *workspace_bytes = p->bwd_workspace_bytes;
@@ -159,6 +179,7 @@ extern "C" int tn_plan_backward_info(tn_plan_t p, int32_t n_wrt, const int32_t* 
 
 extern "C" int tn_plan_num_nodes(tn_plan_t p, int32_t* n) {
   if (!p || !n) return set_err(TN_E_INVALID, "null pointer");
+  PlanLock lk(p->mu);
   *n = (int32_t)p->nodes.size();
   return TN_OK;
 }
@@ -166,6 +187,7 @@ extern "C" int tn_plan_num_nodes(tn_plan_t p, int32_t* n) {
 extern "C" int tn_plan_node_info(tn_plan_t p, int32_t k, int32_t* kernel_class, int32_t* logH, int32_t* logM,
                                  int32_t* logN, int32_t* logK, double* flops, double* bytes) {
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (k < 0 || k >= (int32_t)p->nodes.size()) return set_err(TN_E_INVALID, "node out of range");
   const NodeInfo& ni = p->nodes[k];
   if (kernel_class) *kernel_class = ni.kclass;
@@ -175,6 +197,58 @@ extern "C" int tn_plan_node_info(tn_plan_t p, int32_t k, int32_t* kernel_class, 
   if (logK) *logK = (int32_t)ni.K.size();
   if (flops) *flops = ni.flops;
   if (bytes) *bytes = ni.bytes;
+  return TN_OK;
+}
+
+// Kernel of a forward op, for reporting: symbol-like name and tile variant.
+static const char* op_kernel_name(const tn_plan_s* p, const Op& op, int* tile) {
+  *tile = -1;
+  switch (op.kind) {
+    case OpKind::Row: return op.row.k_split_bits >= 0 ? "splitk_kernel" : "row_kernel";
+    case OpKind::RowReduce: return "reduce_kernel";
+    case OpKind::Gemm:
+      if (gemm_smallk_ok(op.gemm)) return "gemm_smallk";
+      *tile = p->prec == TN_C128 ? kValuTile : op.gemm.tile;
+      return gemm_kernel_name(op.gemm, p->prec);
+    case OpKind::Accum: return "accum_kernel";
+    case OpKind::Permute: return "permute_kernel";
+    case OpKind::Counter: return "counter_kernel";
+    default: return "";
+  }
+}
+
+extern "C" int tn_plan_node_kernel(tn_plan_t p, int32_t k, int32_t* tile, char* name, int32_t name_cap) {
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
+  if (k < 0 || k >= (int32_t)p->nodes.size()) return set_err(TN_E_INVALID, "node out of range");
+  const int node = p->n_leaves + k;
+  const Op* main = nullptr;
+  for (const Op& op : p->fwd)
+    if (op.node == node && (op.kind == OpKind::Gemm || op.kind == OpKind::Row)) { main = &op; break; }
+  if (!main) return set_err(TN_E_INVALID, "node has no contraction op");
+  int t = -1;
+  const char* nm = op_kernel_name(p, *main, &t);
+  if (tile) *tile = t;
+  if (name && name_cap > 0) {
+    std::strncpy(name, nm, (size_t)name_cap - 1);
+    name[name_cap - 1] = 0;
+  }
+  return TN_OK;
+}
+
+extern "C" int tn_plan_tune_trials(tn_plan_t p, int32_t cap, int32_t* n, int32_t* keys, int32_t* tiles,
+                                   int32_t* k_bits, float* ms) {
+  if (!p || !n) return set_err(TN_E_INVALID, "null pointer");
+  PlanLock lk(p->mu);
+  *n = (int32_t)p->tune_trials.size();
+  for (int32_t i = 0; i < *n && i < cap; i++) {
+    const auto& t = p->tune_trials[(size_t)i];
+    if (keys)
+      for (int j = 0; j < 6; j++) keys[6 * i + j] = t.key[(size_t)j];
+    if (tiles) tiles[i] = t.tile;
+    if (k_bits) k_bits[i] = t.k_bits;
+    if (ms) ms[i] = t.ms;
+  }
   return TN_OK;
 }
 
@@ -312,15 +386,23 @@ static hipStream_t capture_stream() {
   return s;
 }
 
-// Run `prog` n_batches times on stream s (graph replay when enabled).
+// Run `prog` n_batches times on stream s: replays of the graph cached for
+// (mode, workspace) when graphs are enabled and `use_graph` is set, else
+// launch by launch.  Called with the plan's lock held.
 static int run_batches(tn_plan_s* p, int mode, const std::vector<Op>& prog, const Ctx& ctx, int64_t n_batches,
-                       hipStream_t s) {
+                       hipStream_t s, bool use_graph = true) {
   if (n_batches <= 0) return TN_OK;
-  if (graphs_enabled()) {
+  if (use_graph && graphs_enabled()) {
     auto key = std::make_pair(mode, ctx.ws);
     auto it = p->graphs.find(key);
-    hipGraphExec_t exec = nullptr;
     if (it == p->graphs.end()) {
+      if (p->graphs.size() >= tn_plan_s::kMaxGraphs) {
+        auto lru = p->graphs.begin();
+        for (auto j = p->graphs.begin(); j != p->graphs.end(); ++j)
+          if (j->second.last_use < lru->second.last_use) lru = j;
+        destroy_graph(lru->second);
+        p->graphs.erase(lru);
+      }
       hipStream_t cs = capture_stream();
       if (!cs) return set_err(TN_E_DEVICE, "could not create the capture stream");
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -335,14 +417,25 @@ static int run_batches(tn_plan_s* p, int mode, const std::vector<Op>& prog, cons
       }
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamEndCapture(cs, &graph));
+      hipGraphExec_t exec = nullptr;
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return set_err(TN_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      p->graphs[key] = exec;
-    } else {
-      exec = (hipGraphExec_t)it->second;
+      hipEvent_t done = nullptr;
+      e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return set_err(TN_E_DEVICE, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e));
+      }
+      tn_plan_s::GraphEntry entry;
+      entry.exec = exec;
+      entry.done = done;
+      it = p->graphs.emplace(key, entry).first;
     }
+    it->second.last_use = ++p->graph_clock;
+    hipGraphExec_t exec = (hipGraphExec_t)it->second.exec;
     for (int64_t b = 0; b < n_batches; b++) HIP_TRY(hipGraphLaunch(exec, s));
+    HIP_TRY(hipEventRecord((hipEvent_t)it->second.done, s));
     return TN_OK;
   }
   for (int64_t b = 0; b < n_batches; b++)
@@ -395,10 +488,12 @@ static int make_ids(const tn_plan_s* p, int64_t n_ids, const int64_t* slice_ids,
   return TN_OK;
 }
 
-extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_t n_ids, const int64_t* slice_ids,
-                                  void* out_c128, void* workspace, uint64_t workspace_bytes, void* stream) {
-  g_err.clear();
-  if (!p) return set_err(TN_E_INVALID, "plan is null");
+// Sliced contraction into out_c128 over `workspace`; with use_graph false
+// every op is launched directly (no graph is captured or instantiated).
+// Called with the plan's lock held.
+static int contract_sliced_impl(tn_plan_s* p, const void* const* leaves, int64_t n_ids, const int64_t* slice_ids,
+                                void* out_c128, void* workspace, uint64_t workspace_bytes, hipStream_t s,
+                                bool use_graph) {
   if (!out_c128) return set_err(TN_E_INVALID, "output is null");
   int rc = check_leaves(p, leaves);
   if (rc) return rc;
@@ -407,14 +502,22 @@ extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_
   std::vector<int64_t> ids;
   rc = make_ids(p, n_ids, slice_ids, ids);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   rc = upload(p, workspace, leaves, out_c128, nullptr, nullptr, 0, ids, s);
   if (rc) return rc;
   const int64_t out_elems = int64_t(1) << (p->n_leaves > 1 ? p->kept_bits[2 * p->n_leaves - 2].size()
                                                            : p->layout[0].bits.size());
   HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(out_c128), (uint64_t)out_elems * 16, s));
   Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
-  return run_batches(p, 1, forward_program(p, 1), ctx, (int64_t)ids.size() / p->n_batch, s);
+  return run_batches(p, 1, forward_program(p, 1), ctx, (int64_t)ids.size() / p->n_batch, s, use_graph);
+}
+
+extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_t n_ids, const int64_t* slice_ids,
+                                  void* out_c128, void* workspace, uint64_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
+  return contract_sliced_impl(p, leaves, n_ids, slice_ids, out_c128, workspace, workspace_bytes,
+                              static_cast<hipStream_t>(stream), true);
 }
 
 static int op_kind_code(const Op& op) {
@@ -436,6 +539,7 @@ extern "C" int tn_contract_sliced_timed(tn_plan_t p, const void* const* leaves, 
                                         int32_t* n_ops) {
   g_err.clear();
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (!out_c128) return set_err(TN_E_INVALID, "output is null");
   int rc = check_leaves(p, leaves);
   if (rc) return rc;
@@ -489,6 +593,7 @@ extern "C" int tn_contract(tn_plan_t p, const void* const* leaves, void* out, vo
                            uint64_t workspace_bytes, void* stream) {
   g_err.clear();
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (p->n_sliced > 0) return set_err(TN_E_INVALID, "plan has sliced indices; use tn_contract_sliced");
   if (!out) return set_err(TN_E_INVALID, "output is null");
   int rc = check_leaves(p, leaves);
@@ -511,6 +616,7 @@ extern "C" int tn_contract_backward(tn_plan_t p, const void* const* leaves, cons
                                     void* stream) {
   g_err.clear();
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (!grad_out_c128) return set_err(TN_E_INVALID, "grad_out is null");
   if (n_wrt > 0 && !grads) return set_err(TN_E_INVALID, "grads is null");
   int rc = check_leaves(p, leaves);
@@ -541,27 +647,34 @@ extern "C" int tn_contract_backward(tn_plan_t p, const void* const* leaves, cons
 // ------------------------------------------------------------------ autotuning
 
 // For every distinct matrix-core contraction shape, time each tile variant on
-// the plan's own operands (zero-filled arena) and keep the fastest.
+// the plan's own operands (zero-filled arena) and keep the fastest.  Each
+// candidate runs with the summed range cut to at most 2^12 values per split
+// (long enough for the kernel's steady state), once to warm up and then in
+// three separately timed launches; the median decides.
 extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_bytes, void* stream) {
   g_err.clear();
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   if (!workspace || workspace_bytes < p->workspace_bytes)
     return set_err(TN_E_WORKSPACE, "workspace of " + std::to_string(p->workspace_bytes) + " bytes required");
   if (p->prec == TN_C128) return TN_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<int64_t> ids(p->n_batch, 0);
-  ids.resize((size_t)std::max<int64_t>(p->n_batch, 1), 0);
-  for (size_t i = 1; i < ids.size(); i++) ids[i] = -1;   // one live slice
+  std::vector<int64_t> ids((size_t)std::max<int64_t>(p->n_batch, 1), -1);
+  ids[0] = 0;   // one live slice
   std::vector<const void*> dummy(p->n_leaves, workspace);
   int rc = upload(p, workspace, dummy.data(), workspace, nullptr, nullptr, 0, ids, s);
   if (rc) return rc;
   HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(workspace) + p->arena_off, p->arena_bytes, s));
   Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  constexpr int kReps = 3;
+  hipEvent_t ev[kReps + 1] = {};
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   std::map<std::array<int, 6>, int> best;
+  std::vector<tn_plan_s::TuneTrial> trials;
+  int result = TN_OK;
+  const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
   for (Op& op : p->fwd) {
+    if (result != TN_OK) break;
     if (op.kind != OpKind::Gemm) continue;
     GemmOp& g = op.gemm;
     if (g.a.kind != 1 || g.b.kind != 1) continue;   // leaf operands: keep the default
@@ -570,44 +683,54 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     if (best.count(key)) continue;
     float best_ms = 1e30f;
     int best_tile = 0;
-    // matrix-core tiles only; the summed range is cut to at most 2^9 values
-    // per split for the trials (time per tile scales with K, the ranking does
-    // not)
-    const bool verbose = std::getenv("TN_TUNE_VERBOSE") != nullptr;
     for (int t = 0; t < kNumGemmTiles; t++) {
       if (t == kValuTile || !gemm_tile_ok(g, t, p->prec)) continue;
       GemmOp trial = g;
       trial.tile = t;
-      trial.n_k = std::min(trial.n_k, 9 + std::max(0, trial.k_split_bits));
-      const int reps = 2;
-      HIP_TRY(launch_gemm(ctx, trial, p->prec, s));   // warm-up
-      HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; r++) HIP_TRY(launch_gemm(ctx, trial, p->prec, s));
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      trial.n_k = std::min(trial.n_k, 12 + std::max(0, trial.k_split_bits));
+      hipError_t e = launch_gemm(ctx, trial, p->prec, s);   // warm-up
+      for (int r = 0; r < kReps && e == hipSuccess; r++) {
+        e = hipEventRecord(ev[r], s);
+        if (e == hipSuccess) e = launch_gemm(ctx, trial, p->prec, s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(ev[kReps], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+      float t_ms[kReps] = {};
+      for (int r = 0; r < kReps && e == hipSuccess; r++) e = hipEventElapsedTime(&t_ms[r], ev[r], ev[r + 1]);
+      if (e != hipSuccess) {
+        result = set_err(TN_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(e));
+        break;
+      }
+      std::sort(t_ms, t_ms + kReps);
+      const float med = t_ms[kReps / 2];
+      tn_plan_s::TuneTrial tr;
+      tr.key = key;
+      tr.tile = t;
+      tr.k_bits = trial.n_k;
+      tr.ms = med;
+      trials.push_back(tr);
       if (verbose)
-        fprintf(stderr, "tune (h,m,n,k)=(%d,%d,%d,%d) tile %d: %.3f ms for k=2^%d\n", g.n_h, g.n_m, g.n_n, g.n_k, t,
-                ms / reps, trial.n_k);
-      if (ms < best_ms) { best_ms = ms; best_tile = t; }
+        fprintf(stderr, "tune (h,m,n,k)=(%d,%d,%d,%d) tile %d: median %.3f ms for k=2^%d\n", g.n_h, g.n_m, g.n_n,
+                g.n_k, t, med, trial.n_k);
+      if (med < best_ms) { best_ms = med; best_tile = t; }
     }
     best[key] = best_tile;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (result != TN_OK) return result;
   p->tile_choice = best;
+  p->tune_trials = trials;
   p->pinned_tile = -1;
   assign_tiles(p, p->fwd);
   if (p->bwd_built) assign_tiles(p, p->bwd);
-  for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
-  p->graphs.clear();
+  drop_graphs(p, -1);
   p->tuned = true;
   return TN_OK;
 }
 
 extern "C" int tn_plan_set_tile(tn_plan_t p, int32_t tile, int32_t* n_set) {
   if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
   int bm, bn;
   if (gemm_tile_bits(tile, &bm, &bn)) return set_err(TN_E_INVALID, "unknown tile variant");
   int32_t n = 0;
@@ -618,16 +741,16 @@ extern "C" int tn_plan_set_tile(tn_plan_t p, int32_t tile, int32_t* n_set) {
         op.gemm.tile = tile;
         n++;
       }
-  if (n) {
-    for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
-    p->graphs.clear();
-  }
+  if (n) drop_graphs(p, -1);
   if (n_set) *n_set = n;
   return TN_OK;
 }
 
 extern "C" void tn_plan_destroy(tn_plan_t p) {
   if (!p) return;
-  for (auto& kv : p->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  {
+    PlanLock lk(p->mu);
+    drop_graphs(p, -1);
+  }
   delete p;
 }

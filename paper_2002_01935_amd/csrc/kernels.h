@@ -19,6 +19,8 @@ hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s);
 int gemm_tile_bits(int tile, int* bm, int* bn);
 // whether tile variant `tile` can run op at precision prec
 bool gemm_tile_ok(const GemmOp& op, int tile, int prec);
+// kernel (template instance) that launch_gemm runs for op's tile at precision prec
+const char* gemm_kernel_name(const GemmOp& op, int prec);
 constexpr int kNumGemmTiles = 10;
 constexpr int kNumTilesShared = 4;   // tiles 0..3 exist for every matrix-core kernel
 constexpr int kValuTile = 4;   // vector-ALU variant (complex128 and reference)

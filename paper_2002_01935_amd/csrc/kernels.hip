@@ -1218,6 +1218,44 @@ bool gemm_tile_ok(const GemmOp& op, int tile, int prec) {
   return true;
 }
 
+const char* gemm_kernel_name(const GemmOp& op, int prec) {
+  if (prec == TN_C128) return "gemm_valu<double>";
+  if (op.tile == kValuTile) return "gemm_valu<float>";
+  if (prec == TN_C64_3M) {
+    switch (op.tile) {
+      case 0: return "gemm_mfma_3m<128,128,2,4>";
+      case 1: return "gemm_mfma_3m<64,128,1,4>";
+      case 2: return "gemm_mfma_3m<128,64,2,2>";
+      case 3: return "gemm_mfma_3m<64,64,1,2>";
+      case 7: return "gemm_mfma_3m_dl<128,128,2,2>";
+      case 8: return "gemm_mfma_3m_dl<256,128,4,2>";
+      case 9: return "gemm_mfma_3m_dl<128,128,2,4,4>";
+      default: return "?";
+    }
+  }
+  if (prec == TN_C64_BF16X3) {
+    switch (op.tile) {
+      case 0: return "gemm_mfma_bf16x3<128,128,8,2,2>";
+      case 1: return "gemm_mfma_bf16x3<64,128,8,1,2,1>";
+      case 2: return "gemm_mfma_bf16x3<128,64,8,2,1>";
+      case 3: return "gemm_mfma_bf16x3<64,64,8,1,1,1>";
+      default: return "?";
+    }
+  }
+  switch (op.tile) {
+    case 0: return "gemm_mfma_4m<128,128,2,2>";
+    case 1: return "gemm_mfma_4m<64,128,1,2>";
+    case 2: return "gemm_mfma_4m<128,64,2,1>";
+    case 3: return "gemm_mfma_4m<64,64,1,1>";
+    case 5: return "gemm_mfma_4m<256,128,4,2>";
+    case 6: return "gemm_mfma_4m<128,128,2,2,1>";
+    case 7: return "gemm_mfma_4m_dl<128,128,2,2>";
+    case 8: return "gemm_mfma_4m_dl<256,128,4,2>";
+    case 9: return "gemm_mfma_4m_dl<128,128,2,2,3>";
+    default: return "?";
+  }
+}
+
 static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec, dim3 grid, hipStream_t s);
 
 hipError_t launch_gemm(const Ctx& ctx, const GemmOp& in, int prec, hipStream_t s) {

@@ -4,6 +4,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,9 +105,30 @@ struct tn_plan_s {
   double bwd_flops_per_slice = 0;
   bool bwd_built = false;
 
-  // cached HIP graphs, keyed by (mode, workspace address)
-  std::map<std::pair<int, uint64_t>, void*> graphs;
+  // Serialises every entry point that reads or changes the mutable state
+  // below (graph cache, backward program, tile choices) or enqueues work.
+  std::mutex mu;
+  // cached HIP graphs, keyed by (mode, workspace address); at most
+  // kMaxGraphs, least recently used evicted first.  `done` is an event
+  // recorded after the entry's latest launch: an entry is destroyed only
+  // after that event has completed, so no graph is freed while it runs.
+  struct GraphEntry {
+    void* exec = nullptr;   // hipGraphExec_t
+    void* done = nullptr;   // hipEvent_t
+    uint64_t last_use = 0;
+  };
+  static constexpr size_t kMaxGraphs = 8;
+  std::map<std::pair<int, uint64_t>, GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   bool tuned = false;
+  // autotune trials of the last tn_plan_tune: shape key (h, m, n, k, split
+  // bits, direct-to-LDS eligible), tile, trial k bits, median ms
+  struct TuneTrial {
+    std::array<int, 6> key;
+    int tile = 0, k_bits = 0;
+    float ms = 0;
+  };
+  std::vector<TuneTrial> tune_trials;
   // matrix-core tile variants: autotuned choice per (h, m, n, k, split bits,
   // direct-to-LDS eligible), applied to the forward and backward programs;
   // a variant pinned by tn_plan_set_tile (-1: none) goes wherever it applies

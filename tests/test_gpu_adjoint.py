@@ -5,7 +5,7 @@ homogeneity identity of a network that is linear in every leaf."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import TOL_C128, TOL_C64, note, rel, to_dev
+from tests.gpu_util import TOL_C128, TOL_C64, c64_leaves, note, rel, rel_inf, to_dev
 from tn_inputs import configs
 from tn_inputs.circuits import circuit_network, gate_leaves
 from tn_inputs.graphs import random_network
@@ -36,12 +36,11 @@ def test_autograd_amplitude_norm(oracle_lib, prec):
     c = contract(plan, leaves)
     L = (c.abs() ** 2).sum()
     L.backward()
-    c_ref = complex(oracle_lib.contract(net, tree))
-    refs = oracle_lib.grad(net, tree, np.array(2 * c_ref), wrt)
+    rnet = net if prec == "c128" else c64_leaves(net)
+    c_ref = complex(oracle_lib.contract(rnet, tree))
+    refs = oracle_lib.grad(rnet, tree, np.array(2 * c_ref), wrt)
     tol = TOL_C128 if prec == "c128" else TOL_C64
-    got = np.concatenate([leaves[v].grad.cpu().numpy().ravel() for v in wrt])
-    ref = np.concatenate([r.ravel() for r in refs])
-    assert rel(got, ref) < tol
+    _per_leaf([leaves[v].grad.cpu().numpy() for v in wrt], refs, tol, "autograd " + prec)
     for v in range(net.n_leaves):
         if v not in wrt:
             assert leaves[v].grad is None
@@ -59,16 +58,15 @@ def test_backward_sliced_hyper_outputs(oracle_lib, seed):
     wrt = list(range(net.n_leaves))
     d = int(np.prod([net.idx_dim[e] for e in sliced]))
     ids = [s for s in range(d) if s % 3 != 1]
-    refs = oracle_lib.grad(net, tree, go, wrt, sliced=sliced, slice_ids=ids)
     import torch
     for prec, tol in (("c128", TOL_C128), ("c64_4m", TOL_C64)):
+        refs = oracle_lib.grad(net if prec == "c128" else c64_leaves(net), tree, go, wrt, sliced=sliced,
+                               slice_ids=ids)
         note("backward sliced", seed, prec)
         plan = _plan(net, tree, sliced, prec, nb=2)
         grads = plan.backward(to_dev(net, prec), torch.from_numpy(go), wrt, slice_ids=ids)
         torch.cuda.synchronize()
-        got = np.concatenate([g.cpu().numpy().ravel() for g in grads])
-        ref = np.concatenate([r.ravel() for r in refs])
-        assert rel(got, ref) < tol
+        _per_leaf([g.cpu().numpy() for g in grads], refs, tol, "backward sliced %d %s" % (seed, prec))
 
 
 def test_backward_bitwise_independent_of_batch():
@@ -88,15 +86,30 @@ def test_backward_bitwise_independent_of_batch():
         assert np.array_equal(o, outs[0])
 
 
+def _per_leaf(got, ref, tol, what):
+    """Each leaf's gradient on its own: normwise and max-componentwise
+    relative errors within tol; returns the worst of each."""
+    w2 = wi = 0.0
+    for v, (g, r) in enumerate(zip(got, ref)):
+        e2, ei = rel(g, r), rel_inf(g, r)
+        w2, wi = max(w2, e2), max(wi, ei)
+        assert e2 < tol and ei < tol, (what, v, e2, ei)
+    note(what, "per-leaf worst rel %.3e, max-componentwise %.3e" % (w2, wi))
+    return w2, wi
+
+
 def test_cfg4_gradient_full_size(oracle_lib):
     """6x6 grid, 12 cycles, width 28: d|amp|^2 / d(every fSim leaf) in
     complex64 through tn_contract_backward (recomputation from checkpoints).
-    Checks: (i) homogeneity, (ii) central differences on the GPU complex128
-    path (h = 1e-4; |amp|^2 is quadratic in each entry, so exact up to
-    rounding), (iii) the oracle's complex128 gradient on two sub-slices of the
-    same tree (more indices sliced on both sides)."""
+    Checks, each leaf on its own: (i) homogeneity, (ii) central differences
+    on the GPU complex128 path (h = 1e-4; |amp|^2 is quadratic in each entry,
+    so exact up to rounding), (iii) the oracle's complex128 gradient on two
+    sub-slices of the same tree (more indices sliced on both sides).  The
+    references use the same complex64-rounded leaves the complex64 plan
+    receives."""
     import torch
     net, tree, sliced = configs.load("cfg4")
+    net64 = c64_leaves(net)
     wrt = gate_leaves(net, "2q")
     assert len(wrt) == 180
     plan64 = _plan(net, tree, sliced, "c64_4m")
@@ -108,19 +121,24 @@ def test_cfg4_gradient_full_size(oracle_lib):
     grads = plan64.backward(leaves, torch.tensor(2 * c, dtype=torch.complex128), wrt)
     torch.cuda.synchronize()
     grads = [g.cpu().numpy() for g in grads]
-    # (i) homogeneity: c is linear in each gate, so sum_k G_k conj(grad_k) = 2 L
-    worst = 0.0
+    # (i) homogeneity: c is linear in each gate, so sum_k G_k conj(grad_k) = 2 L.
+    # The sum over a gate's 16 entries cancels (its terms have random phases),
+    # so a relative error d of the gradient entries moves it by up to
+    # d * sum_k |G_k| |grad_k|: that is the scale the identity is held to.
+    worst = worst_rel = 0.0
     for v, g in zip(wrt, grads):
-        h = np.sum(net.leaves[v].ravel() * g.ravel().conj())
-        worst = max(worst, abs(h - 2 * L) / (2 * L))
-    note("cfg4 homogeneity worst rel", worst)
-    assert worst < 1e-4
-    # (ii) finite differences with the complex128 GPU path
+        terms = net64.leaves[v].ravel() * g.ravel().conj()
+        h = np.sum(terms)
+        worst = max(worst, abs(h - 2 * L) / np.abs(terms).sum())
+        worst_rel = max(worst_rel, abs(h - 2 * L) / (2 * L))
+    note("cfg4 homogeneity worst error %.3e relative to sum |G||grad| (%.3e relative to 2L)" % (worst, worst_rel))
+    assert worst < TOL_C64
+    # (ii) finite differences with the complex128 GPU path on the same leaves
     plan128 = _plan(net, tree, sliced, "c128")
-    leaves128 = to_dev(net, "c128")
+    leaves128 = to_dev(net64, "c128")
     hstep = 1e-4
     fd_err = 0.0
-    for v, k in ((wrt[0], 5), (wrt[90], 10), (wrt[179], 15)):
+    for v, k in ((wrt[0], 5), (wrt[90], 10), (wrt[179], 15), (wrt[45], 0), (wrt[135], 6)):
         g = grads[wrt.index(v)].ravel()[k]
         parts = []
         for step in (hstep, 1j * hstep):
@@ -133,21 +151,22 @@ def test_cfg4_gradient_full_size(oracle_lib):
                 vals.append(abs(complex(plan128.contract_sliced(ls).cpu().numpy())) ** 2)
             parts.append((vals[0] - vals[1]) / (2 * hstep))
         fd = parts[0] + 1j * parts[1]
-        fd_err = max(fd_err, abs(fd - g) / max(abs(fd), 1e-30))
-    note("cfg4 finite-difference worst rel", fd_err)
-    assert fd_err < 1e-3
-    # (iii) oracle gradient on sub-slices of the same tree
+        scale = np.abs(grads[wrt.index(v)]).max()
+        fd_err = max(fd_err, abs(fd - g) / scale)
+    note("cfg4 finite-difference worst error relative to the leaf's largest entry", fd_err)
+    assert fd_err < TOL_C64
+    # (iii) oracle gradient on sub-slices of the same tree, leaf by leaf
     ext = extend_slices(net, tree, sliced, 30.0)
     ids = [0, 5]
     go = np.array(2 * c)
     sub = _plan(net, tree, ext, "c64_4m")
     g_sub = sub.backward(leaves, torch.from_numpy(go), wrt, slice_ids=ids)
     torch.cuda.synchronize()
-    ref = oracle_lib.grad(net, tree, go, wrt, sliced=ext, slice_ids=ids)
-    got = np.concatenate([x.cpu().numpy().ravel() for x in g_sub])
-    refv = np.concatenate([r.ravel() for r in ref])
-    note("cfg4 sub-slice gradient rel err", rel(got, refv))
-    assert rel(got, refv) < 1e-4
+    ref = oracle_lib.grad(net64, tree, go, wrt, sliced=ext, slice_ids=ids)
+    got = [x.cpu().numpy() for x in g_sub]
+    note("cfg4 sub-slice gradient rel err (all leaves)",
+         rel(np.concatenate([x.ravel() for x in got]), np.concatenate([r.ravel() for r in ref])))
+    _per_leaf(got, ref, TOL_C64, "cfg4 sub-slice gradient")
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c64_3m"])

@@ -432,3 +432,65 @@ def test_subtree_values_compose_to_root(oracle_lib):
         tot = tot + np.einsum(spec, a, b)
     assert rel(tot, full) < 1e-12
     assert n == net.n_leaves
+
+
+def _kappa_cases():
+    """(network, tree, sliced, kappa in closed form) with the root's children
+    known by construction: two leaves whose product is the root."""
+    rng = np.random.default_rng(12)
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    u = rng.normal(size=8) + 1j * rng.normal(size=8)
+    v = rng.normal(size=8) + 1j * rng.normal(size=8)
+    dot = Network([u, v], [[0], [0]], [8], [])
+    k_dot = np.linalg.norm(u) * np.linalg.norm(v) / abs(np.dot(u, v))
+    # index 1 (dimension 4) sliced: per slice b the children are u[:, b], v[:, b]
+    U = rng.normal(size=(8, 4)) + 1j * rng.normal(size=(8, 4))
+    V = rng.normal(size=(8, 4)) + 1j * rng.normal(size=(8, 4))
+    sliced = Network([U, V], [[0, 1], [0, 1]], [8, 4], [])
+    k_sl = sum(np.linalg.norm(U[:, b]) * np.linalg.norm(V[:, b]) for b in range(4)) / abs(np.sum(U * V))
+    # open output o: R[o] = sum_a U[a, o] v[a], kappa = ||U|| ||v|| / ||R||
+    opened = Network([U, v], [[0, 1], [0]], [8, 4], [1])
+    k_open = np.linalg.norm(U) * np.linalg.norm(v) / np.linalg.norm(v @ U)
+    # nearly orthogonal vectors: a large kappa (heavy cancellation)
+    w = v - np.vdot(u.conj(), v) / np.vdot(u.conj(), u.conj()) * u.conj() + 1e-3 * u.conj()
+    ortho = Network([u, w], [[0], [0]], [8], [])
+    k_ortho = np.linalg.norm(u) * np.linalg.norm(w) / abs(np.dot(u, w))
+    return [(dot, two, [], k_dot), (sliced, two, [1], k_sl), (opened, two, [], k_open), (ortho, two, [], k_ortho)]
+
+
+def test_root_condition_closed_forms(oracle_lib):
+    """kappa = sum over slices of ||T_l|| ||T_r|| / ||R|| for the root's
+    children: a dot product, the same with an index sliced (sum of per-slice
+    norm products), an open output, and a nearly orthogonal pair (kappa in
+    the hundreds)."""
+    for i, (net, tree, sl, k) in enumerate(_kappa_cases()):
+        got = oracle_lib.root_condition(net, tree, sl)
+        assert abs(got - k) <= 1e-12 * k, (i, got, k)
+    assert _kappa_cases()[3][3] > 100
+
+
+@pytest.mark.parametrize("mistake", ["left_twice", "slice_ignored", "abs_of_sum"])
+def test_root_condition_catches_planted_mistakes(oracle_lib, monkeypatch, mistake):
+    """A plausible mistake planted in the evaluator behind kappa fails the
+    closed-form pins: both children read from the left subtree, the slice id
+    ignored (every slice's children taken from slice 0), or the result norm
+    taken over the absolute values (no cancellation)."""
+    from oracle import contract as oc
+    real_sub, real_contract = oc.subtree_value, oc.contract
+    if mistake == "left_twice":
+        def sub(net, tree, node, sliced=(), slice_id=None):
+            return real_sub(net, tree, int(tree.left[-1]), sliced, slice_id)
+        monkeypatch.setattr(oc, "subtree_value", sub)
+    elif mistake == "slice_ignored":
+        def sub(net, tree, node, sliced=(), slice_id=None):
+            return real_sub(net, tree, node, sliced, 0 if sliced else slice_id)
+        monkeypatch.setattr(oc, "subtree_value", sub)
+    else:
+        def con(net, tree, **kw):
+            return np.abs(real_contract(net.with_leaves([np.abs(t) for t in net.leaves]), tree, **kw))
+        monkeypatch.setattr(oc, "contract", con)
+    caught = 0
+    for net, tree, sl, k in _kappa_cases():
+        if abs(oc.root_condition(net, tree, sl) - k) > 1e-6 * k:
+            caught += 1
+    assert caught >= 1, mistake
