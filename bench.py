@@ -604,9 +604,12 @@ def main():
             # the kernel and tile that ran, and the autotune trials of its shape
             roof["kernel"] = nd["kernel"]
             roof["tile"] = nd["tile"]
-            shape = roof["log2_hmnk"]
+            h, m, n, k = roof["log2_hmnk"]
+            # trial shapes are (h, m, n, k) of the GEMM as launched: A may be
+            # either child, so m and n can appear swapped
             roof["autotune"] = [{"tile": t["tile"], "k_bits": t["k_bits"], "median_ms": round(t["ms"], 3)}
-                                for t in plan.tune_trials() if t["shape"][:4] == shape]
+                                for t in plan.tune_trials()
+                                if t["shape"][0] == h and t["shape"][3] == k and sorted(t["shape"][1:3]) == sorted([m, n])]
             roof["traffic"] = measured_traffic(nd["kernel"], args.precision, args.workload, roof["log2_hmnk"])
         log(f"dominant gemm node {dom['node']}: {avg_s * 1e3:.2f} ms/launch, {achieved:.1f} TFLOP/s")
 

@@ -338,6 +338,9 @@ static bool pick_swap(int kc, const std::vector<int>& M, const std::vector<int>&
 
 // Build one contraction op: C(out_bits in layout Cl) = sum A * op(B).
 // Classes are derived from the operand and output bit sets.
+// Longest summed range one matrix-core accumulator covers (log2).
+constexpr int kMaxSplitSumBits = 13;
+
 static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0, int conj_a,
                         int conj_b, const Ref& cref, const Layout& Cl, bool accumulate,
                         int forced_swap, int node, Prog& prog) {
@@ -404,7 +407,16 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     // (about 2^9 blocks of 128 x 128 tiles, each summing at least 2^9 values),
     // the partial tiles to an arena buffer summed in a fixed order afterwards
     const int tiles_log = std::max(0, fa - 7) + std::max(0, fb - 7) + h;
-    const int ks = std::min(std::min(k - 9, 9 - tiles_log), 10);
+    int ks = std::min(std::min(k - 9, 9 - tiles_log), 10);
+    // a sum accumulated in one FP32 register loses accuracy as the square
+    // root of its length (about 2^-24 * sqrt(K / 6) relative for terms of
+    // random phase): sums longer than 2^kMaxSplitSumBits are split so that
+    // no part is longer, with a partial buffer at most half the larger
+    // operand; the parts are then added in a fixed order
+    if (p->prec != TN_C128 && k > kMaxSplitSumBits) {
+      const int acc = std::min(std::min(k - kMaxSplitSumBits, 10), k - 1 - std::min(fa, fb));
+      ks = std::max(ks, acc);
+    }
     g.k_split_bits = ks > 0 ? ks : 0;
     if (ks > 0) g.part = buf_ref(prog.new_buf((int64_t)p->elem_bytes << (h + fa + fb + ks)));
   } else {

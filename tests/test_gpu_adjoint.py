@@ -124,7 +124,10 @@ def test_cfg4_gradient_full_size(oracle_lib):
     # (i) homogeneity: c is linear in each gate, so sum_k G_k conj(grad_k) = 2 L.
     # The sum over a gate's 16 entries cancels (its terms have random phases),
     # so a relative error d of the gradient entries moves it by up to
-    # d * sum_k |G_k| |grad_k|: that is the scale the identity is held to.
+    # d * sum_k |G_k| |grad_k|: that is the scale the identity is held to.  Its
+    # two sides are two complex64 computations of c (the forward value, and
+    # sum_k G_k E_k from the reverse pass), each within TOL_C64 of the oracle,
+    # so they may differ by twice that.
     worst = worst_rel = 0.0
     for v, g in zip(wrt, grads):
         terms = net64.leaves[v].ravel() * g.ravel().conj()
@@ -132,7 +135,7 @@ def test_cfg4_gradient_full_size(oracle_lib):
         worst = max(worst, abs(h - 2 * L) / np.abs(terms).sum())
         worst_rel = max(worst_rel, abs(h - 2 * L) / (2 * L))
     note("cfg4 homogeneity worst error %.3e relative to sum |G||grad| (%.3e relative to 2L)" % (worst, worst_rel))
-    assert worst < TOL_C64
+    assert worst < 2 * TOL_C64
     # (ii) finite differences with the complex128 GPU path on the same leaves
     plan128 = _plan(net, tree, sliced, "c128")
     leaves128 = to_dev(net64, "c128")
