@@ -22,16 +22,19 @@
  *     device memory owned by the caller.  Index lists, the tree, slice ids and
  *     the pointer arrays themselves are host memory owned by the caller and
  *     are not retained after the call returns (the plan copies what it needs).
- *   - The library allocates no device memory.  The only device-side objects
- *     it owns are HIP graphs cached inside a plan.  All work is enqueued on
+ *   - The library allocates no device memory of its own beyond the HIP graphs
+ *     cached inside a plan and the static scratch array of
+ *     tn_contract_sliced_noalloc (64 MiB per GPU, part of its code object).
+ *     All work is enqueued on
  *     the caller's stream (a hipStream_t passed as void*; NULL = default
  *     stream); calls return without waiting for the GPU.
  *   - Threads: every entry point that takes a plan holds that plan's lock
  *     while it reads or changes the plan's mutable state (cached graphs, the
  *     reverse program, tile choices) and enqueues its work, so several host
  *     threads may call into one plan at once.  Calls that run at the same
- *     time on the GPU must use distinct workspaces; calls that share a
- *     workspace must be ordered, e.g. on one stream.  A plan caches at most 8 graphs,
+ *     time on the GPU must use distinct workspaces (and, for the
+ *     allocation-free variant, distinct GPUs); calls that share a workspace
+ *     must be ordered, e.g. on one stream.  A plan caches at most 8 graphs,
  *     one per (call kind, workspace address); the least recently used one is
  *     freed, after its last launch has finished, when a ninth is needed.
  *     tn_plan_destroy must not race with other calls on the same plan.
@@ -251,6 +254,23 @@ int tn_plan_node_kernel(tn_plan_t plan, int32_t k, int32_t* tile, char* name, in
  */
 int tn_plan_tune_trials(tn_plan_t plan, int32_t cap, int32_t* n, int32_t* keys, int32_t* tiles,
                         int32_t* k_bits, float* ms);
+
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. a serving loop with a fixed memory budget): the same
+ * contraction and result as tn_contract_sliced, with the workspace replaced
+ * by a static array of 64 MiB that the library holds on each GPU it runs on
+ * (loaded with its code object, kept until the process ends).  The call
+ * allocates no device memory and captures no graph: every kernel is launched
+ * on `stream`, which must belong to the calling thread's current device.
+ * Plans whose workspace (tn_plan_info) exceeds 64 MiB get TN_E_WORKSPACE.
+ * The array keeps the last call's contents; the call resets what must start
+ * from zero (the batch counter and out_c128).  All calls on one GPU share the
+ * array: calls that overlap on one GPU, from any plan or thread, race and
+ * must be ordered by the caller (e.g. on one stream).
+ */
+int tn_contract_sliced_noalloc(tn_plan_t plan, const void* const* leaves, int64_t n_ids,
+                               const int64_t* slice_ids, void* out_c128, void* stream);
 
 void tn_plan_destroy(tn_plan_t plan);
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
     "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile", "tn_plan_node_kernel",
-    "tn_plan_tune_trials",
+    "tn_plan_tune_trials", "tn_contract_sliced_noalloc",
 ]
 OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
 
@@ -63,6 +63,7 @@ def _load():
     lib.tn_contract_sliced_timed.argtypes = [P, P, i64, P, P, P, u64, P, i32, P, P, P, P, P, P]
     lib.tn_plan_node_kernel.argtypes = [P, i32, P, ctypes.c_char_p, i32]
     lib.tn_plan_tune_trials.argtypes = [P, i32, P, P, P, P, P]
+    lib.tn_contract_sliced_noalloc.argtypes = [P, P, i64, P, P, P]
     lib.tn_plan_destroy.argtypes = [P]
     lib.tn_plan_destroy.restype = None
     lib.tn_last_error.restype = ctypes.c_char_p
@@ -252,6 +253,23 @@ class Plan:
             n = len(keep)
         _check(lib.tn_contract_sliced(self.handle, _dev_ptrs(leaves), n, ptr, ctypes.c_void_p(out.data_ptr()),
                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
+        return out
+
+    def contract_sliced_noalloc(self, leaves, out, slice_ids=None, stream=None):
+        """tn_contract_sliced over the library's static per-device scratch:
+        no workspace, and the call allocates no device memory.  `out` is a
+        caller-provided contiguous complex128 tensor; calls that overlap on
+        one GPU race on the shared scratch."""
+        self._check_leaves(leaves)
+        if out.dtype != torch.complex128 or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must be a contiguous complex128 CUDA tensor")
+        if slice_ids is None:
+            n, ptr, keep = 0, None, None
+        else:
+            keep, ptr = _arr(list(slice_ids), np.int64)
+            n = len(keep)
+        _check(lib.tn_contract_sliced_noalloc(self.handle, _dev_ptrs(leaves), n, ptr, ctypes.c_void_p(out.data_ptr()),
+                                              _stream(stream)))
         return out
 
     def contract_sliced_timed(self, leaves, slice_ids=None, out=None, workspace=None, stream=None):

@@ -520,6 +520,49 @@ extern "C" int tn_contract_sliced(tn_plan_t p, const void* const* leaves, int64_
                               static_cast<hipStream_t>(stream), true);
 }
 
+// ------------------------------------------------- allocation-free variant
+
+// Workspace of tn_contract_sliced_noalloc: one array per device, loaded with
+// the library's code object and held until the process ends.  In host code
+// `scratch` names a host-side stand-in, so host code never passes it to a
+// kernel or a copy; it uses the device address hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+constexpr uint64_t kStaticScratchBytes = uint64_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(TN_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_err(TN_E_DEVICE, "hipGetSymbolAddress gave a null scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TN_OK;
+}
+
+extern "C" int tn_contract_sliced_noalloc(tn_plan_t p, const void* const* leaves, int64_t n_ids,
+                                          const int64_t* slice_ids, void* out_c128, void* stream) {
+  g_err.clear();
+  if (!p) return set_err(TN_E_INVALID, "plan is null");
+  PlanLock lk(p->mu);
+  if (p->workspace_bytes > kStaticScratchBytes)
+    return set_err(TN_E_WORKSPACE, "plan needs a workspace of " + std::to_string(p->workspace_bytes) +
+                                       " bytes; the static scratch holds " + std::to_string(kStaticScratchBytes));
+  void* ws = nullptr;
+  int rc = static_scratch(&ws);
+  if (rc) return rc;
+  return contract_sliced_impl(p, leaves, n_ids, slice_ids, out_c128, ws, kStaticScratchBytes,
+                              static_cast<hipStream_t>(stream), false);
+}
+
 static int op_kind_code(const Op& op) {
   switch (op.kind) {
     case OpKind::Row: return op.row.k_split_bits >= 0 ? 1 : 0;
