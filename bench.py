@@ -258,12 +258,16 @@ def summarize_rocprof(path):
     if trace:
         total = sum(sum(v) for v in trace.values())
         out.append(f"kernel trace: {sum(len(v) for v in trace.values())} dispatches, {total:.1f} ms total")
+        # `long` = dispatches within 10 % of the group's longest: the full-size
+        # launches, apart from shortened ones of the same kernel and grid
+        # (autotune trials run with the summed range cut)
         out.append(f"{'kernel':52s} {'grid x,y,z / wg':26s} {'calls':>6s} {'mean ms':>10s} {'min ms':>10s} "
-                   f"{'total ms':>10s} {'share':>6s}")
+                   f"{'total ms':>10s} {'share':>6s} {'long n':>6s} {'long mean':>10s}")
         for (k, g), v in sorted(trace.items(), key=lambda kv: -sum(kv[1]))[:30]:
             gs = f"{g[0]},{g[1]},{g[2]}/{g[3]}"
+            lv = [x for x in v if x >= 0.9 * max(v)]
             out.append(f"{k[:52]:52s} {gs:26s} {len(v):6d} {sum(v) / len(v):10.3f} {min(v):10.3f} "
-                       f"{sum(v):10.1f} {sum(v) / total:6.1%}")
+                       f"{sum(v):10.1f} {sum(v) / total:6.1%} {len(lv):6d} {sum(lv) / len(lv):10.3f}")
     if pmc:
         out.append("PMC counters (mean per dispatch, KiB for FETCH_SIZE / WRITE_SIZE):")
         agg = []
@@ -441,11 +445,13 @@ def sampling_bench(n_samples):
 
 
 def qaoa_bench(n, p, n_streams):
-    """QAOA MAX-CUT energy (Sec. 4.4) on a seeded random 3-regular graph: one
+    """QAOA MAX-CUT energy (Sec. 4.5) on a seeded random 3-regular graph: one
     light-cone network per edge, each with its own tree and plan (complex64
-    4M), contracted back to back on one stream and round-robin over
-    `n_streams` streams (default priority, one workspace per plan); the many
-    small networks make it launch-latency bound."""
+    4M), contracted back to back on one stream, round-robin over `n_streams`
+    streams (default priority, one workspace per plan), and all terms in one
+    graph launch (tn_batch: tiny contractions in the interpreter kernel, one
+    workgroup per term); plan by plan the many small networks are
+    launch-latency bound."""
     import numpy as np
     import torch
 
@@ -485,10 +491,34 @@ def qaoa_bench(n, p, n_streams):
             ts.append(time.perf_counter() - t1)
         res[name + "_s"] = round(sorted(ts)[1], 5)
     energy = float(sum(complex(o.item()).real for o in outs))
+    # every term in one graph launch (tn_batch), on one stream
+    from paper_2002_01935_amd.binding import Batch
+    t0 = time.perf_counter()
+    batch = Batch(plans)
+    bws = batch.workspace()
+    batch.prepare(bws)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    bouts = batch.contract(leaves, bws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t1 = time.perf_counter()
+        batch.contract(leaves, bws, outs=bouts)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    res["batched_one_stream_s"] = round(sorted(ts)[2], 5)
+    binfo = batch.info()
+    e_batch = float(sum(complex(o.item()).real for o in bouts))
     print(json.dumps({"mode": "qaoa", "workload": f"MAX-CUT QAOA, random 3-regular graph N={n}, p={p}, seed 0",
                       "terms": len(plans), "leaves_per_term_max": max(len(l) for l in leaves),
                       "flops_8C_total": flops, "plan_s": round(t_plan, 2), **res,
-                      "tflops_best": round(flops / min(res.values()) / 1e12, 4), "energy": energy}))
+                      "batch": {"prepare_s": round(t_prep, 3), "launches_per_call": binfo["launches"],
+                                "interpreter_levels": binfo["levels"], "interpreted_contractions": binfo["tiny_ops"],
+                                "workspace_MiB": round(binfo["workspace_bytes"] / 2 ** 20, 1),
+                                "launches_per_term_unbatched": round(sum(len(pl.nodes()) for pl in plans) / len(plans), 1)},
+                      "tflops_best": round(flops / min(res.values()) / 1e12, 4), "energy": energy,
+                      "energy_batched": e_batch}))
 
 
 def main():

@@ -73,11 +73,20 @@ typedef enum {
     TN_C128 = 3
 } tn_precision;
 
+/* tn_options.flags */
+enum {
+    /* GEMM-shaped contractions (both free sides of at least 32 values) go to
+       the matrix-core or few-summed-values kernels whatever their size.  By
+       default those under 2^25 complex multiply-adds run on the row kernel,
+       whose launches cost a fraction of a matrix-core launch at that size. */
+    TN_FLAG_GEMM_ALL_SIZES = 1
+};
+
 typedef struct {
     int32_t prec;                /* tn_precision */
     int32_t autotune;            /* nonzero: tn_plan_tune may retune tile shapes */
     int32_t max_inflight_slices; /* slices contracted together per launch; 0 = choose from workspace_cap */
-    int32_t reserved;
+    int32_t flags;               /* TN_FLAG_* */
     uint64_t workspace_cap;      /* bytes; 0 = no cap (in-flight slices default to 1) */
 } tn_options;
 
@@ -271,6 +280,42 @@ int tn_plan_tune_trials(tn_plan_t plan, int32_t cap, int32_t* n, int32_t* keys, 
  */
 int tn_contract_sliced_noalloc(tn_plan_t plan, const void* const* leaves, int64_t n_ids,
                                const int64_t* slice_ids, void* out_c128, void* stream);
+
+/*
+ * Many independent small networks in one graph launch (Sec. 4.5: the QAOA
+ * energy is a sum of one light-cone network per edge; Sec. 4.7.3: sampling
+ * needs many contractions).  A batch takes n_plans compiled, unsliced plans
+ * of one precision (TN_E_UNSUPPORTED for a sliced plan, TN_E_INVALID for
+ * mixed precisions); it copies their programs (with their tile choices at
+ * this time), so the plans may be destroyed afterwards.  Each network's
+ * contractions with at most 2^14 (outputs x summed values) run inside one
+ * interpreter kernel, one workgroup per network, in the network's own order;
+ * the others with the ordinary kernels between the interpreter's launches.
+ * The result of network j is its tn_contract result.
+ *
+ * tn_batch_info: workspace bytes, number of interpreter launches (levels),
+ * number of contractions the interpreter runs, and launches per call.
+ *
+ * tn_batch_prepare: writes the batch's tables (contraction descriptors and
+ * per-network launch contexts) into `workspace` and captures the graph for
+ * that workspace address (at most 8 workspaces per batch; the least recently
+ * used is dropped, after its last launch has finished).  The caller must not
+ * modify a prepared workspace between calls.
+ *
+ * tn_batch_contract: leaves = the leaf pointers of network 0 (in leaf
+ * order), then of network 1, ...; outs[j] = network j's output, in its plan's
+ * storage type and out_idx order.  `workspace` must have been prepared
+ * (TN_E_WORKSPACE otherwise).  Uploads the pointer tables and replays the
+ * graph on `stream`.  Calls on one workspace must be ordered.
+ */
+typedef struct tn_batch_s* tn_batch_t;
+int tn_batch(int32_t n_plans, const tn_plan_t* plans, tn_batch_t* batch);
+int tn_batch_info(tn_batch_t batch, uint64_t* workspace_bytes, int32_t* n_levels, int64_t* n_tiny,
+                  int64_t* n_launches);
+int tn_batch_prepare(tn_batch_t batch, void* workspace, uint64_t workspace_bytes, void* stream);
+int tn_batch_contract(tn_batch_t batch, const void* const* leaves, void* const* outs, void* workspace,
+                      uint64_t workspace_bytes, void* stream);
+void tn_batch_destroy(tn_batch_t batch);
 
 void tn_plan_destroy(tn_plan_t plan);
 

@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtn.so")
 
 TN_C64_4M, TN_C64_3M, TN_C64_BF16X3, TN_C128 = 0, 1, 2, 3
+TN_FLAG_GEMM_ALL_SIZES = 1
 PRECISIONS = {"c64_4m": TN_C64_4M, "c64_3m": TN_C64_3M, "c64_bf16x3": TN_C64_BF16X3, "c128": TN_C128}
 KERNEL_CLASSES = {0: "row", 1: "splitk", 2: "gemm", 3: "gemm_splitk"}
 
@@ -28,7 +29,8 @@ EXPORTS = [
     "tn_plan", "tn_plan_info", "tn_plan_backward_info", "tn_plan_num_nodes", "tn_plan_node_info",
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
     "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile", "tn_plan_node_kernel",
-    "tn_plan_tune_trials", "tn_contract_sliced_noalloc",
+    "tn_plan_tune_trials", "tn_contract_sliced_noalloc", "tn_batch", "tn_batch_info", "tn_batch_prepare",
+    "tn_batch_contract", "tn_batch_destroy",
 ]
 OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
 
@@ -41,7 +43,7 @@ class TNError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("max_inflight_slices", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_inflight_slices", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("workspace_cap", ctypes.c_uint64)]
 
 
@@ -64,11 +66,17 @@ def _load():
     lib.tn_plan_node_kernel.argtypes = [P, i32, P, ctypes.c_char_p, i32]
     lib.tn_plan_tune_trials.argtypes = [P, i32, P, P, P, P, P]
     lib.tn_contract_sliced_noalloc.argtypes = [P, P, i64, P, P, P]
+    lib.tn_batch.argtypes = [i32, P, ctypes.POINTER(P)]
+    lib.tn_batch_info.argtypes = [P, P, P, P, P]
+    lib.tn_batch_prepare.argtypes = [P, P, u64, P]
+    lib.tn_batch_contract.argtypes = [P, P, P, P, u64, P]
+    lib.tn_batch_destroy.argtypes = [P]
+    lib.tn_batch_destroy.restype = None
     lib.tn_plan_destroy.argtypes = [P]
     lib.tn_plan_destroy.restype = None
     lib.tn_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("tn_plan_destroy", "tn_last_error"):
+        if name not in ("tn_plan_destroy", "tn_last_error", "tn_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -117,7 +125,7 @@ class Plan:
     .right (SSA pairs, leaves first)."""
 
     def __init__(self, net, tree, sliced=(), precision="c64_4m", max_inflight_slices=0,
-                 workspace_cap=0, autotune=False):
+                 workspace_cap=0, autotune=False, gemm_all_sizes=False):
         rank, leaf_idx, idx_dim, out_idx = net.flat()
         self.n_leaves = int(len(rank))
         self.out_shape = tuple(int(idx_dim[e]) for e in out_idx)
@@ -135,7 +143,8 @@ class Plan:
             arr, ptr = _arr(a, dt)
             keep.append(arr)
             args.append(ptr)
-        opt = _Options(self.prec, int(bool(autotune)), int(max_inflight_slices), 0, int(workspace_cap))
+        flags = TN_FLAG_GEMM_ALL_SIZES if gemm_all_sizes else 0
+        opt = _Options(self.prec, int(bool(autotune)), int(max_inflight_slices), flags, int(workspace_cap))
         handle = ctypes.c_void_p()
         _check(lib.tn_plan(self.n_leaves, args[0], args[1], int(len(idx_dim)), args[2], int(len(out_idx)),
                            args[3], args[4], args[5], int(len(keep[6])), args[6], ctypes.byref(opt),
@@ -145,7 +154,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:   # lib is None during interpreter shutdown
             lib.tn_plan_destroy(h)
             self.handle = None
 
@@ -319,3 +328,50 @@ class Plan:
                                         _dev_ptrs(grads), n, ptr, ctypes.c_void_p(workspace.data_ptr()),
                                         workspace.numel(), _stream(stream)))
         return grads
+
+
+class Batch:
+    """Many unsliced plans of one precision contracted by one graph launch
+    (tn_batch): tiny contractions in an interpreter kernel (one workgroup per
+    network), large ones with the ordinary kernels."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)   # kept for shapes and dtypes only
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        _check(lib.tn_batch(len(self.plans), arr, ctypes.byref(handle)))
+        self.handle = handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lib is not None:
+            lib.tn_batch_destroy(h)
+            self.handle = None
+
+    def info(self) -> dict:
+        ws, lv, nt, nl = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.tn_batch_info(self.handle, ctypes.byref(ws), ctypes.byref(lv), ctypes.byref(nt), ctypes.byref(nl)))
+        return dict(workspace_bytes=ws.value, levels=lv.value, tiny_ops=nt.value, launches=nl.value)
+
+    def workspace(self, stream=None):
+        n = self.info()["workspace_bytes"]
+        return _on_stream(stream, lambda: torch.empty(max(n, 1), dtype=torch.uint8, device="cuda"))
+
+    def prepare(self, workspace, stream=None):
+        _check(lib.tn_batch_prepare(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    _stream(stream)))
+
+    def contract(self, leaves, workspace, outs=None, stream=None):
+        """leaves[j] = the leaf tensors of plan j; returns the outputs."""
+        if len(leaves) != len(self.plans):
+            raise ValueError(f"expected leaves of {len(self.plans)} networks")
+        flat = []
+        for p, ls in zip(self.plans, leaves):
+            p._check_leaves(ls)
+            flat.extend(ls)
+        if outs is None:
+            outs = [_on_stream(stream, lambda p=p: torch.empty(p.out_shape, dtype=p.storage_dtype, device="cuda"))
+                    for p in self.plans]
+        _check(lib.tn_batch_contract(self.handle, _dev_ptrs(flat), _dev_ptrs(outs), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), _stream(stream)))
+        return outs

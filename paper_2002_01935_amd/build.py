@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtn.so")
-SOURCES = ["plan.cpp", "kernels.hip", "smallk.hip", "exec.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "smallk.hip", "exec.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -21,6 +21,7 @@
 #include <string>
 #include <vector>
 
+#include "exec.h"
 #include "kernels.h"
 #include "plan.h"
 #include "smallk.h"
@@ -42,6 +43,8 @@ static int set_err(int code, const std::string& msg) {
   } while (0)
 
 extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
+
+int tn::set_error(int code, const std::string& msg) { return set_err(code, msg); }
 
 using PlanLock = std::lock_guard<std::mutex>;
 
@@ -254,7 +257,7 @@ extern "C" int tn_plan_tune_trials(tn_plan_t p, int32_t cap, int32_t* n, int32_t
 
 // ------------------------------------------------------------------ launching
 
-static Ctx make_ctx(const tn_plan_s* p, void* ws, uint64_t arena_stride) {
+Ctx tn::make_ctx(const tn_plan_s* p, void* ws, uint64_t arena_stride) {
   Ctx c;
   std::memset(&c, 0, sizeof c);
   c.ws = reinterpret_cast<uint64_t>(ws);
@@ -268,13 +271,13 @@ static Ctx make_ctx(const tn_plan_s* p, void* ws, uint64_t arena_stride) {
   return c;
 }
 
-static hipError_t launch_op(const tn_plan_s* p, const Ctx& ctx, const Op& op, hipStream_t s) {
-  const bool f64 = p->prec == TN_C128;
+hipError_t tn::launch_op(int prec, const Ctx& ctx, const Op& op, hipStream_t s) {
+  const bool f64 = prec == TN_C128;
   switch (op.kind) {
     case OpKind::Row: return launch_row(ctx, op.row, f64, s);
     case OpKind::RowReduce: return launch_reduce(ctx, op.row, f64, s);
     case OpKind::Gemm:
-      return gemm_smallk_ok(op.gemm) ? launch_gemm_smallk(ctx, op.gemm, p->prec, s) : launch_gemm(ctx, op.gemm, p->prec, s);
+      return gemm_smallk_ok(op.gemm) ? launch_gemm_smallk(ctx, op.gemm, prec, s) : launch_gemm(ctx, op.gemm, prec, s);
     case OpKind::Accum: return launch_accum(ctx, op.accum, f64, s);
     case OpKind::Permute: return launch_permute(ctx, op.perm, f64, s);
     case OpKind::Fill: return hipSuccess;
@@ -283,10 +286,14 @@ static hipError_t launch_op(const tn_plan_s* p, const Ctx& ctx, const Op& op, hi
   return hipErrorInvalidValue;
 }
 
+static hipError_t launch_op(const tn_plan_s* p, const Ctx& ctx, const Op& op, hipStream_t s) {
+  return tn::launch_op(p->prec, ctx, op, s);
+}
+
 // Tail of the forward program: what happens to each in-flight slice's root.
 // mode 0: copy to the output slot in the storage type (unsliced contraction)
 // mode 1: FP64 accumulation into the complex128 output slot
-static std::vector<Op> forward_program(const tn_plan_s* p, int mode) {
+std::vector<Op> tn::forward_program(const tn_plan_s* p, int mode) {
   std::vector<Op> prog = p->fwd;
   const int n = p->n_leaves;
   Ref root;

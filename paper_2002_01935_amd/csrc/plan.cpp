@@ -312,16 +312,23 @@ struct Operand {
   Layout lay;
 };
 
-static int kernel_class(int prec, int m, int n, int k, int h) {
-  (void)k;
-  (void)h;
-  (void)prec;
+// Smallest GEMM-shaped contraction (log2 complex multiply-adds) that goes to
+// the matrix-core or few-summed-values kernels.  A matrix-core launch of a
+// small node costs about 20 us however little it computes (a one-block launch
+// streams ~30 KB of unrolled kernel code through a cold instruction cache),
+// against about 4 us for the row kernel; below ~2^25 multiply-adds the row
+// kernel's lower throughput does not catch up (measured: cfg2 +17 %, cfg3 and
+// cfg5h unchanged, QAOA terms -11 %).
+constexpr int kMinGemmBits = 25;
+
+static int kernel_class(const tn_plan_s* p, int m, int n, int k, int h) {
+  const int min_bits = (p->opt.flags & TN_FLAG_GEMM_ALL_SIZES) ? 0 : kMinGemmBits;
   // two wide free sides: a GEMM op.  With many summed values a matrix-core
   // tile reuses each B value across its rows, where the row kernel would
   // reload it; with at most four (an outer product included) the product is
   // bound by the write of C and runs on the few-summed-values kernel, whose
   // threads keep their own operand values in registers across 16 rows
-  if (m >= 5 && n >= 5) return kGemm;
+  if (m >= 5 && n >= 5 && h + m + n + k >= min_bits) return kGemm;
   return kRow;   // row or split-K, refined below
 }
 
@@ -367,7 +374,7 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
   byC(M);
   byC(N);
   const int h = (int)H.size(), m = (int)M.size(), n = (int)N.size(), k = (int)K.size();
-  int kc = kernel_class(p->prec, m, n, k, h);
+  int kc = kernel_class(p, m, n, k, h);
   bool swap = false;
   if (forced_swap >= 0) swap = forced_swap != 0;
   else swap = pick_swap(kc, M, N, H, cb);
@@ -531,7 +538,7 @@ static void assign_layouts(tn_plan_s* p) {
     };
     std::vector<int> H = ni.H, M = ni.M, N = ni.N, K = ni.K;
     byC(H); byC(M); byC(N);
-    int kc = kernel_class(p->prec, (int)M.size(), (int)N.size(), (int)K.size(), (int)H.size());
+    int kc = kernel_class(p, (int)M.size(), (int)N.size(), (int)K.size(), (int)H.size());
     const bool swap = pick_swap(kc, M, N, H, Cl.bits);
     ni.kclass = kc;
     ni.swap = swap;

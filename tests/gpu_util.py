@@ -84,20 +84,22 @@ def to_dev(net, precision):
     return [torch.from_numpy(np.ascontiguousarray(t)).to(device="cuda", dtype=dt).contiguous() for t in net.leaves]
 
 
-def gpu_sliced(net, tree, sliced=(), slice_ids=None, precision="c64_4m", max_inflight=0, plan=None):
+def gpu_sliced(net, tree, sliced=(), slice_ids=None, precision="c64_4m", max_inflight=0, plan=None,
+               gemm_all_sizes=False):
     import torch
     from paper_2002_01935_amd.binding import Plan
-    p = plan or Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=max_inflight)
+    p = plan or Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=max_inflight,
+                     gemm_all_sizes=gemm_all_sizes)
     leaves = to_dev(net, precision)
     out = p.contract_sliced(leaves, slice_ids=slice_ids)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
 
-def gpu_contract(net, tree, precision="c64_4m"):
+def gpu_contract(net, tree, precision="c64_4m", gemm_all_sizes=False):
     import torch
     from paper_2002_01935_amd.binding import Plan
-    p = Plan(net, tree, precision=precision)
+    p = Plan(net, tree, precision=precision, gemm_all_sizes=gemm_all_sizes)
     out = p.contract(to_dev(net, precision))
     torch.cuda.synchronize()
     return out.cpu().numpy()

@@ -15,9 +15,9 @@ from tn_inputs.slicing import extend_slices
 pytestmark = pytest.mark.gpu
 
 
-def _plan(net, tree, sliced=(), precision="c64_4m", nb=0):
+def _plan(net, tree, sliced=(), precision="c64_4m", nb=0, gemm_all_sizes=False):
     from paper_2002_01935_amd.binding import Plan
-    return Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=nb)
+    return Plan(net, tree, sliced=sliced, precision=precision, max_inflight_slices=nb, gemm_all_sizes=gemm_all_sizes)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64_4m"])
@@ -194,7 +194,7 @@ def test_backward_direct_to_lds(oracle_lib, prec):
         refs = oracle_lib.grad(net, two, go, [0, 1])
         ref = np.concatenate([r.ravel() for r in refs])
         for t in (7, 8, 9):
-            plan = _plan(net, two, precision=prec)
+            plan = _plan(net, two, precision=prec, gemm_all_sizes=True)
             plan.backward_info([0, 1])
             plan.set_tile(0)           # off the direct-to-LDS default, so that pinning t changes the op
             changed = plan.set_tile(t)
@@ -225,7 +225,7 @@ def test_backward_split_k(oracle_lib, prec):
     net = Network([a, b], [M + K, K + N], [2] * (m + n + k), M + N)
     go = rng.normal(size=(2,) * (m + n)) + 1j * rng.normal(size=(2,) * (m + n))
     ref = oracle_lib.grad(net, two, go, [0])[0]
-    plan = _plan(net, two, precision=prec)
+    plan = _plan(net, two, precision=prec, gemm_all_sizes=True)
     note("backward split-k", prec)
     g1 = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0])[0].cpu().numpy()
     g2 = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0])[0].cpu().numpy()

@@ -72,11 +72,9 @@ def _refs(name, oracle_lib):
     return _memo[key]
 
 
-@pytest.mark.parametrize("name", ["cfg5", "cfg5h", "cfg3"])
-@pytest.mark.parametrize("prec", ["c64_4m", "c64_3m", "c64_bf16x3"])
+@pytest.mark.parametrize("name,prec", [("cfg5", "c64_4m"), ("cfg5", "c64_3m"), ("cfg5", "c64_bf16x3"),
+                                       ("cfg5h", "c64_4m"), ("cfg3", "c64_4m")])
 def test_full_slice(oracle_lib, name, prec):
-    if name != "cfg5" and prec != "c64_4m":
-        pytest.skip("3M and BF16x3 at full size: cfg5 only")
     got = _gpu_slice(name, prec)
     ref, ref128 = _refs(name, oracle_lib)
     note(name, prec, "vs the complex128 circuit: rel %.3e max-componentwise %.3e"

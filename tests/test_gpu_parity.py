@@ -33,13 +33,17 @@ TOLS = {"c64_4m": TOL_C64, "c128": TOL_C128, "c64_bf16x3": TOL_BF16X3, "c64_3m":
 def test_pairwise(oracle_lib, shape, prec):
     net = pairwise_network(*shape, seed=sum(shape) * 7 + len(prec))
     ref = oracle_lib.contract(net, TWO)
-    note("pairwise", shape, prec)
     tol = TOLS[prec]
-    got = gpu_sliced(net, TWO, precision=prec)
-    assert got.shape == ref.shape
-    assert rel(got, ref) < tol
-    got2 = gpu_contract(net, TWO, precision=prec)
-    assert rel(got2, ref) < tol
+    # the default kernel choice, and the matrix-core kernels for GEMM-shaped
+    # nodes of every size (by default those under 2^25 multiply-adds take the
+    # row kernel)
+    for all_sizes in (False, True):
+        note("pairwise", shape, prec, "gemm_all_sizes", all_sizes)
+        got = gpu_sliced(net, TWO, precision=prec, gemm_all_sizes=all_sizes)
+        assert got.shape == ref.shape
+        assert rel(got, ref) < tol
+        got2 = gpu_contract(net, TWO, precision=prec, gemm_all_sizes=all_sizes)
+        assert rel(got2, ref) < tol
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])
@@ -127,7 +131,7 @@ def test_every_tile_variant(oracle_lib, prec):
     for ni, (net, tree, sl) in enumerate(nets):
         ref = oracle_lib.contract(net, tree, sliced=sl)
         for t in TILE_CASES[prec]:
-            plan = Plan(net, tree, sliced=sl, precision=prec)
+            plan = Plan(net, tree, sliced=sl, precision=prec, gemm_all_sizes=True)
             changed = plan.set_tile(t)   # 0 when no contraction can take it, or t is already every op's default
             note("tile", prec, t, "net", ni, "changed", changed)
             got = gpu_sliced(net, tree, sliced=sl, precision=prec, plan=plan)
@@ -239,19 +243,19 @@ def test_gemm_split_k(oracle_lib, prec):
     cases += [(_canonical_pair(0, 7, 7, 12, seed=5), "canonical"), (_canonical_pair(1, 6, 7, 11, seed=6), "canonical h")]
     for net, name in cases:
         note("split-k", prec, name)
-        plan = Plan(net, TWO, precision=prec)
+        plan = Plan(net, TWO, precision=prec, gemm_all_sizes=True)
         assert [n["kclass"] for n in plan.nodes()] == ["gemm_splitk"], name
         ref = oracle_lib.contract(net, TWO)
         assert rel(gpu_sliced(net, TWO, precision=prec, plan=plan), ref) < TOLS[prec], name
-        assert rel(gpu_contract(net, TWO, precision=prec), ref) < TOLS[prec], name
+        assert rel(gpu_contract(net, TWO, precision=prec, gemm_all_sizes=True), ref) < TOLS[prec], name
     net = pairwise_network(0, 8, 7, 12, seed=40, dims=(2,))
     k_idx = [e for e in range(net.n_idx) if e not in net.out_idx]
     sl = k_idx[:1]
-    plan = Plan(net, TWO, sliced=sl, precision=prec, max_inflight_slices=2)
+    plan = Plan(net, TWO, sliced=sl, precision=prec, max_inflight_slices=2, gemm_all_sizes=True)
     assert [n["kclass"] for n in plan.nodes()] == ["gemm_splitk"]
     ref = oracle_lib.contract(net, TWO, sliced=sl)
     note("split-k sliced", prec)
-    assert rel(gpu_sliced(net, TWO, sliced=sl, precision=prec, max_inflight=2), ref) < TOLS[prec]
+    assert rel(gpu_sliced(net, TWO, sliced=sl, precision=prec, max_inflight=2, plan=plan), ref) < TOLS[prec]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128", "c64_3m", "c64_bf16x3"])
@@ -301,10 +305,11 @@ def test_graph_replays_match_eager(oracle_lib, monkeypatch):
         ids = list(range(0, 2 ** len(sl), 3)) if len(sl) > 2 else list(range(2 ** len(sl)))
         ref = oracle_lib.contract(net, tree, sliced=sl, slice_ids=ids)
         monkeypatch.setenv("TN_NO_GRAPH", "1")
-        eager = gpu_sliced(net, tree, sliced=sl, slice_ids=ids, precision="c64_4m", max_inflight=2)
+        eager = gpu_sliced(net, tree, sliced=sl, slice_ids=ids, precision="c64_4m", max_inflight=2,
+                           gemm_all_sizes=True)
         monkeypatch.delenv("TN_NO_GRAPH")
         assert rel(eager, ref) < TOL_C64, ci
-        plan = Plan(net, tree, sliced=sl, precision="c64_4m", max_inflight_slices=2)
+        plan = Plan(net, tree, sliced=sl, precision="c64_4m", max_inflight_slices=2, gemm_all_sizes=True)
         for r in range(4):
             note("graph replay", ci, "call", r)
             got = gpu_sliced(net, tree, sliced=sl, slice_ids=ids, plan=plan)

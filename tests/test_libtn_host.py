@@ -59,8 +59,12 @@ def test_node_classes(B):
     nodes = B.Plan(net, tree).nodes()
     assert len(nodes) == 119
     for n in nodes:
-        big = min(n["logM"], n["logN"]) >= 5
+        # GEMM-shaped (both free sides >= 32) and at least 2^25 multiply-adds
+        big = min(n["logM"], n["logN"]) >= 5 and n["logH"] + n["logM"] + n["logN"] + n["logK"] >= 25
         assert n["kclass"].startswith("gemm") == big
+    everything = B.Plan(net, tree, gemm_all_sizes=True).nodes()
+    for n in everything:
+        assert n["kclass"].startswith("gemm") == (min(n["logM"], n["logN"]) >= 5)
         assert n["flops"] == 8 * 2 ** (n["logH"] + n["logM"] + n["logN"] + n["logK"])
 
 
@@ -170,17 +174,18 @@ def _canonical_pair(m, n, k, k_first=False):
 def test_set_tile(B):
     two = Tree(np.array([0], np.int32), np.array([1], np.int32))
     net = _canonical_pair(7, 7, 5)
-    p = B.Plan(net, two, precision="c64_4m")
+    assert [n["kclass"] for n in B.Plan(net, two, precision="c64_4m").nodes()] == ["row"]   # 2^19 multiply-adds
+    p = B.Plan(net, two, precision="c64_4m", gemm_all_sizes=True)
     assert [n["kclass"] for n in p.nodes()] == ["gemm"]
     assert p.set_tile(7) == 1          # direct-to-LDS variant applies: summed bits lowest
     assert p.set_tile(7) == 0          # already set
     assert p.set_tile(0) == 1
-    p3 = B.Plan(net, two, precision="c64_3m")
+    p3 = B.Plan(net, two, precision="c64_3m", gemm_all_sizes=True)
     assert p3.set_tile(5) == 0         # 4M-only variant
     assert p3.set_tile(7) == 0         # 3M direct-to-LDS: already the default
     assert p3.set_tile(9) == 1
     assert p3.set_tile(1) == 1
-    q = B.Plan(_canonical_pair(7, 7, 5, k_first=True), two, precision="c64_4m")
+    q = B.Plan(_canonical_pair(7, 7, 5, k_first=True), two, precision="c64_4m", gemm_all_sizes=True)
     assert q.set_tile(8) == 0          # summed bits not lowest in A
     assert q.set_tile(5) == 1
     with pytest.raises(B.TNError) as e:
@@ -197,9 +202,13 @@ def test_split_k_gemm_plan(B):
     assert [n["kclass"] for n in p.nodes()] == ["gemm_splitk"]
     # 2^5 splits (top summed bits) of the 2^14 complex64 outputs
     assert p.info()["workspace_bytes"] >= 8 << (14 + 5)
-    assert [n["kclass"] for n in B.Plan(_canonical_pair(7, 7, 9), two).nodes()] == ["gemm"]
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(7, 7, 9), two, gemm_all_sizes=True).nodes()] == ["gemm"]
     assert [n["kclass"] for n in B.Plan(_canonical_pair(10, 10, 14), two).nodes()] == ["gemm_splitk"]   # 64 tiles
-    assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 14), two).nodes()] == ["gemm"]
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 13), two).nodes()] == ["gemm"]
+    # more than 2^13 summed values: split for accuracy even with many tiles
+    # (each part sums at most 2^13 values)
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 14), two).nodes()] == ["gemm_splitk"]
+    assert [n["kclass"] for n in B.Plan(_canonical_pair(12, 12, 14), two, precision="c128").nodes()] == ["gemm"]
     assert [n["kclass"] for n in B.Plan(pairwise_network(0, 8, 7, 11, seed=1), two).nodes()] == ["gemm_splitk"]
 
 
