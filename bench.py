@@ -381,7 +381,7 @@ def node_bench(spec, precision, reps):
     # variant that applies is timed here instead
     per_tile = {}
     best = None
-    for t in (range(10) if node["kclass"].startswith("gemm") else [0]):
+    for t in (range(13) if node["kclass"].startswith("gemm") else [0]):
         if t == 4 or (t and plan.set_tile(t) == 0 and t != 0):
             continue
         if t == 0:
@@ -392,7 +392,7 @@ def node_bench(spec, precision, reps):
             _, ops = plan.contract_sliced_timed(leaves, out=out, workspace=ws)
             # the contraction's own kernels (split-K includes its reduction),
             # not the FP64 accumulation of the root into the output
-            cops = [o for o in ops if o["kind"] in ("row", "splitk", "reduce", "gemm")]
+            cops = [o for o in ops if o["kind"] in ("row", "splitk", "reduce", "gemm", "split")]
             op = dict(max(cops, key=lambda o: o["flops"]), ms=sum(o["ms"] for o in cops))
             tbest = op if tbest is None or op["ms"] < tbest["ms"] else tbest
         per_tile[t] = round(tbest["ms"], 4)
@@ -726,10 +726,15 @@ def main():
             vg = max((o for o in vops if o["kind"] == "gemm"), key=lambda o: o["ms"])
             vt = vg["flops"] * EXECUTED[prec] / (vg["ms"] / 1e3 / B) / 1e12
             vnd = vp.nodes()[vg["node"] - net.n_leaves]
+            vshape = [vnd["logH"], vnd["logM"], vnd["logN"], vnd["logK"]]
             rec["roofline"] = {"bound": "mfma", "kernel": vnd["kernel"], "tile": vnd["tile"], "node": vg["node"],
                                "achieved": round(vt, 2), "peak": PEAK[prec], "unit": "TFLOP/s",
                                "frac": round(vt / PEAK[prec], 4), "executed_per_8C": EXECUTED[prec],
-                               "avg_launch_ms": round(vg["ms"] / B, 3)}
+                               "avg_launch_ms": round(vg["ms"] / B, 3), "log2_hmnk": vshape,
+                               "autotune": [{"tile": t["tile"], "k_bits": t["k_bits"], "median_ms": round(t["ms"], 3)}
+                                            for t in vp.tune_trials()
+                                            if t["shape"][0] == vshape[0] and t["shape"][3] == vshape[3]
+                                            and sorted(t["shape"][1:3]) == sorted(vshape[1:3])]}
             if plain_ref is not None:
                 v1 = vp.contract_sliced(leaves, slice_ids=[ids_all[0]], out=out, workspace=vws).cpu().numpy()
                 rec["rel_err_vs_fp64_plain_same_leaves"] = float(np.linalg.norm(v1 - plain_ref)

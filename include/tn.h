@@ -158,8 +158,10 @@ int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t*
 /*
  * Optional autotune pass: times the candidate tile shapes of every distinct
  * matrix-core contraction shape of the forward program on synthetic data in
- * `workspace` (summed range cut to at most 2^12 values per split; one warm-up
- * launch, then the median of three timed launches; tn_plan_tune_trials
+ * `workspace` (one warm-up launch with the summed range cut to at most 2^12
+ * values per split, then the median of three timed launches taken
+ * round-robin over the candidates, at the full summed range when the trials
+ * of a shape fit about 6 s, else at the cut range; tn_plan_tune_trials
  * reports the table) and keeps the fastest in the plan, for the forward and the
  * backward program (contractions of the same shape, split and operand
  * layout class).  Without it, a contraction takes the direct-to-LDS variant
@@ -177,7 +179,11 @@ int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void
  * TN_C64_4M also 5 = 256x128 and 6 = 128x128 with raised matrix-core
  * priority; for TN_C64_4M and TN_C64_3M 7 = 128x128, 8 = 256x128 and
  * 9 = 128x128 at more waves per SIMD, all direct-to-LDS (operands whose
- * summed indices are their lowest axes).  *n_set (may be NULL) receives the
+ * summed indices are their lowest axes); for TN_C64_BF16X3, on operands
+ * split into bf16 planes beforehand, all direct-to-LDS: 10 = 128x128,
+ * 11 = 256x128 (the default), 12 = 128x128 with three stages in flight (the
+ * planner splits the operands of contractions of at least 2^28
+ * multiply-adds, which then run on variants 10-12 only; the others take 0-4).  *n_set (may be NULL) receives the
  * number of contractions changed.  TN_E_INVALID for an unknown variant.  Used to test
  * every variant and to reproduce a tuned plan.
  */
@@ -234,7 +240,8 @@ int tn_contract_backward(tn_plan_t plan, const void* const* leaves,
  * n_ops receives the number of ops of one batch's program and, for i <
  * min(n_ops, cap), op_ms[i] the summed duration of op i over all batches,
  * op_kind[i] its kernel (0 row, 1 split-K, 2 split-K reduce, 3 GEMM,
- * 4 FP64 accumulation, 5 permute, 6 batch counter), op_node[i] its tree node
+ * 4 FP64 accumulation, 5 permute, 6 batch counter, 7 BF16x3 operand split),
+ * op_node[i] its tree node
  * (-1 if none), op_flops[i] / op_bytes[i] its algorithmic complex FLOPs and
  * bytes per in-flight slice.  Any output array may be NULL.
  */

@@ -32,7 +32,7 @@ EXPORTS = [
     "tn_plan_tune_trials", "tn_contract_sliced_noalloc", "tn_batch", "tn_batch_info", "tn_batch_prepare",
     "tn_batch_contract", "tn_batch_destroy",
 ]
-OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter"}
+OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter", 7: "split"}
 
 
 class TNError(RuntimeError):

@@ -202,7 +202,7 @@ static bool as_tiny(const Op& op, int prec, TinyOp& t) {
   }
   if (op.kind == OpKind::Gemm) {
     const GemmOp& g = op.gemm;
-    if (g.k_split_bits > 0) return false;
+    if (g.k_split_bits > 0 || g.ab_split) return false;
     t.n_out = g.n_h + g.n_m + g.n_n;
     t.n_k = g.n_k;
     if (t.n_out > kTinyBits || t.n_k > kTinyBits || t.n_out + t.n_k > kTinyWorkBits) return false;

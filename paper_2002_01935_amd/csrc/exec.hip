@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -137,7 +138,8 @@ extern "C" int tn_plan_info(tn_plan_t p, int32_t* W, int32_t* W_s, double* log2_
 // Tile variant of every matrix-core contraction of a program: the pinned
 // variant where it applies, else the autotuned one of its shape, else the
 // direct-to-LDS variant where the operands allow it (4M at three waves per
-// SIMD, 3M with 64 x 64 waves), else the register-staged 128 x 128 tile.
+// SIMD, 3M with 64 x 64 waves, BF16x3 on pre-split operands 256 x 128), else
+// the register-staged 128 x 128 tile.
 static std::array<int, 6> tile_key(const GemmOp& g, int prec) {
   return {g.n_h, g.n_m, g.n_n, g.n_k, g.k_split_bits, gemm_tile_ok(g, 7, prec) ? 1 : 0};
 }
@@ -152,7 +154,8 @@ static void assign_tiles(tn_plan_s* p, std::vector<Op>& prog) {
     else if (it != p->tile_choice.end()) t = it->second;
     else if (p->prec == TN_C64_4M && gemm_tile_ok(g, 9, p->prec)) t = 9;
     else if (p->prec == TN_C64_3M && gemm_tile_ok(g, 7, p->prec)) t = 7;
-    g.tile = gemm_tile_ok(g, t, p->prec) ? t : 0;
+    else if (g.ab_split && gemm_tile_ok(g, kSplitTile + 1, p->prec)) t = kSplitTile + 1;
+    g.tile = gemm_tile_ok(g, t, p->prec) ? t : (g.ab_split ? kSplitTile : 0);
   }
 }
 
@@ -216,6 +219,7 @@ static const char* op_kernel_name(const tn_plan_s* p, const Op& op, int* tile) {
     case OpKind::Accum: return "accum_kernel";
     case OpKind::Permute: return "permute_kernel";
     case OpKind::Counter: return "counter_kernel";
+    case OpKind::Split: return "split_kernel";
     default: return "";
   }
 }
@@ -282,6 +286,7 @@ hipError_t tn::launch_op(int prec, const Ctx& ctx, const Op& op, hipStream_t s) 
     case OpKind::Permute: return launch_permute(ctx, op.perm, f64, s);
     case OpKind::Fill: return hipSuccess;
     case OpKind::Counter: return launch_counter(ctx, 1, 1, s);
+    case OpKind::Split: return launch_split(ctx, op.split, s);
   }
   return hipErrorInvalidValue;
 }
@@ -578,6 +583,7 @@ static int op_kind_code(const Op& op) {
     case OpKind::Accum: return 4;
     case OpKind::Permute: return 5;
     case OpKind::Counter: return 6;
+    case OpKind::Split: return 7;
     default: return -1;
   }
 }
@@ -698,9 +704,10 @@ extern "C" int tn_contract_backward(tn_plan_t p, const void* const* leaves, cons
 
 // For every distinct matrix-core contraction shape, time each tile variant on
 // the plan's own operands (zero-filled arena) and keep the fastest.  Each
-// candidate runs with the summed range cut to at most 2^12 values per split
-// (long enough for the kernel's steady state), once to warm up and then in
-// three separately timed launches; the median decides.
+// candidate runs once to warm up with the summed range cut to at most 2^12
+// values per split, then in three separately timed launches, taken
+// round-robin over the candidates, at the full summed range when all of
+// them fit a budget of about 6 s, else at the cut range; the median decides.
 extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_bytes, void* stream) {
   g_err.clear();
   if (!p) return set_err(TN_E_INVALID, "plan is null");
@@ -717,6 +724,7 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
   HIP_TRY(launch_fill(reinterpret_cast<uint64_t>(workspace) + p->arena_off, p->arena_bytes, s));
   Ctx ctx = make_ctx(p, workspace, p->arena_bytes);
   constexpr int kReps = 3;
+  constexpr double kTuneBudgetMs = 6000;   // trials of one shape at the full summed range
   hipEvent_t ev[kReps + 1] = {};
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   std::map<std::array<int, 6>, int> best;
@@ -731,38 +739,65 @@ extern "C" int tn_plan_tune(tn_plan_t p, void* workspace, uint64_t workspace_byt
     if (gemm_smallk_ok(g)) continue;                // few summed values: no tile to choose
     const std::array<int, 6> key = tile_key(g, p->prec);
     if (best.count(key)) continue;
+    // candidates are timed round-robin, one launch each per round, so that a
+    // drift of the clock (it falls under sustained matrix-core load) affects
+    // every candidate alike; the median of three rounds decides
+    std::vector<int> cand;
+    for (int t = 0; t < kNumGemmTiles; t++)
+      if (t != kValuTile && gemm_tile_ok(g, t, p->prec)) cand.push_back(t);
+    std::vector<std::array<float, kReps>> t_ms(cand.size());
+    hipError_t e = hipSuccess;
+    // warm-up, each candidate once with the summed range cut to 2^12 per
+    // split, timed: if every trial at the full range fits the budget, the
+    // trials run at the full range (under sustained load the clock settles
+    // lower than in a short launch, and a kernel's rank can change with it)
+    const int cut_k = std::min(g.n_k, 12 + std::max(0, g.k_split_bits));
+    float warm_max = 0;
+    for (size_t c = 0; c < cand.size() && e == hipSuccess; c++) {
+      GemmOp trial = g;
+      trial.tile = cand[c];
+      trial.n_k = cut_k;
+      float ms = 0;
+      e = hipEventRecord(ev[0], s);
+      if (e == hipSuccess) e = launch_gemm(ctx, trial, p->prec, s);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      warm_max = std::max(warm_max, ms);
+    }
+    const double full_est = (double)warm_max * std::exp2((double)(g.n_k - cut_k)) * (double)cand.size() * kReps;
+    const int trial_k = full_est <= kTuneBudgetMs ? g.n_k : cut_k;
+    for (int r = 0; r < kReps && e == hipSuccess; r++)
+      for (size_t c = 0; c < cand.size() && e == hipSuccess; c++) {
+        GemmOp trial = g;
+        trial.tile = cand[c];
+        trial.n_k = trial_k;
+        e = hipEventRecord(ev[0], s);
+        if (e == hipSuccess) e = launch_gemm(ctx, trial, p->prec, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t_ms[c][(size_t)r], ev[0], ev[1]);
+      }
+    if (e != hipSuccess) {
+      result = set_err(TN_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(e));
+      break;
+    }
     float best_ms = 1e30f;
     int best_tile = 0;
-    for (int t = 0; t < kNumGemmTiles; t++) {
-      if (t == kValuTile || !gemm_tile_ok(g, t, p->prec)) continue;
-      GemmOp trial = g;
-      trial.tile = t;
-      trial.n_k = std::min(trial.n_k, 12 + std::max(0, trial.k_split_bits));
-      hipError_t e = launch_gemm(ctx, trial, p->prec, s);   // warm-up
-      for (int r = 0; r < kReps && e == hipSuccess; r++) {
-        e = hipEventRecord(ev[r], s);
-        if (e == hipSuccess) e = launch_gemm(ctx, trial, p->prec, s);
-      }
-      if (e == hipSuccess) e = hipEventRecord(ev[kReps], s);
-      if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
-      float t_ms[kReps] = {};
-      for (int r = 0; r < kReps && e == hipSuccess; r++) e = hipEventElapsedTime(&t_ms[r], ev[r], ev[r + 1]);
-      if (e != hipSuccess) {
-        result = set_err(TN_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(e));
-        break;
-      }
-      std::sort(t_ms, t_ms + kReps);
-      const float med = t_ms[kReps / 2];
+    for (size_t c = 0; c < cand.size(); c++) {
+      std::array<float, kReps> v = t_ms[c];
+      std::sort(v.begin(), v.end());
+      const float med = v[kReps / 2];
       tn_plan_s::TuneTrial tr;
       tr.key = key;
-      tr.tile = t;
-      tr.k_bits = trial.n_k;
+      tr.tile = cand[c];
+      tr.k_bits = trial_k;
       tr.ms = med;
       trials.push_back(tr);
       if (verbose)
         fprintf(stderr, "tune (h,m,n,k)=(%d,%d,%d,%d) tile %d: median %.3f ms for k=2^%d\n", g.n_h, g.n_m, g.n_n,
-                g.n_k, t, med, trial.n_k);
-      if (med < best_ms) { best_ms = med; best_tile = t; }
+                g.n_k, cand[c], med, tr.k_bits);
+      if (med < best_ms) { best_ms = med; best_tile = cand[c]; }
     }
     best[key] = best_tile;
   }

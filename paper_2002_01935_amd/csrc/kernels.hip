@@ -985,6 +985,204 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0][0][0][0]), acc, wm, wn, tid, NT);
 }
 
+// ------------------------------------------------------------------ BF16x3 on pre-split operands
+
+// Splits a complex64 GEMM operand into the bf16 hi / lo units of SplitOp
+// (tn_internal.h): one thread per row and group of four summed values.
+__global__ __launch_bounds__(256) void split_kernel(Ctx ctx, SplitOp op) {
+  const uint64_t q = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int gbits = op.n_k - 2;                    // groups of four summed values per row
+  if (q >> (op.n_rows + gbits)) return;
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const uint64_t r = q >> gbits, kg = q & ((uint64_t(1) << gbits) - 1);
+  GMEM const float2* S = reinterpret_cast<GMEM const float2*>(resolve(ctx, op.src, z, sid, 8));
+  GMEM u32x4* D = reinterpret_cast<GMEM u32x4*>(resolve(ctx, op.dst, z, sid, 8));
+  const uint64_t base = deposit_runs(r, op.run_row) + deposit_runs(kg, op.run_khi);
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+  u32x4 hi, lo;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const float2 v = ld(S + base + op.j_off[j]);
+    const float re = v.x, im = op.conj ? -v.y : v.y;
+    const bf2v hb = __builtin_convertvector(f2v{re, im}, bf2v);      // round to nearest even
+    const f2v back = __builtin_convertvector(hb, f2v);
+    const bf2v lb = __builtin_convertvector(f2v{re - back.x, im - back.y}, bf2v);
+    hi[j] = __builtin_bit_cast(uint32_t, hb);                           // re in the low half
+    lo[j] = __builtin_bit_cast(uint32_t, lb);
+  }
+  const uint64_t kb = kg >> 1, g = kg & 1;
+  const uint64_t blk = (r << (op.n_k - 3)) + kb;
+  if (op.patterns == 1) {
+    GMEM u32x4* d = D + blk * 4 + 2 * g;
+    d[0] = hi;
+    d[1] = lo;
+  } else {
+    // (re, -im): flip the sign of the high half; (im, re): swap the halves
+    u32x4 h0, l0, h1, l1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      h0[j] = hi[j] ^ 0x80000000u;
+      l0[j] = lo[j] ^ 0x80000000u;
+      h1[j] = (hi[j] >> 16) | (hi[j] << 16);
+      l1[j] = (lo[j] >> 16) | (lo[j] << 16);
+    }
+    GMEM u32x4* d = D + blk * 8 + 2 * g;
+    d[0] = h0;
+    d[1] = l0;
+    d[4] = h1;
+    d[5] = l1;
+  }
+}
+
+// Direct-to-LDS ring for the pre-split BF16x3 operands: per stage (8 summed
+// values) a tile row of A is 4 units (64 contiguous bytes), a tile column of
+// B 8 units (128 contiguous bytes).  LDS slot swizzles (each group of 16
+// lanes of a fragment read hits 16 different 16-byte bank groups): A unit u
+// of row r at r * 4 + (u ^ ((r >> 2) & 3)); B unit u = 4 p + v of column c
+// at c * 8 + 4 p + (v ^ ((c >> 1) & 3)).
+__device__ __forceinline__ int sa_unit(int r, int u) { return r * 4 + (u ^ ((r >> 2) & 3)); }
+__device__ __forceinline__ int sb_unit(int c, int p, int v) { return c * 8 + 4 * p + (v ^ ((c >> 1) & 3)); }
+
+template <int BM, int BN, int NW, int NB>
+struct SplitRing {
+  static constexpr int UA = BM * 4, UB = BN * 8;          // 16-byte units per stage
+  static constexpr int IA = UA / 64 / NW, IB = UB / 64 / NW;
+  static constexpr int NBUF = NB;                          // NB - 1 stages in flight
+  static constexpr int UNITS = UA + UB;
+  static_assert(IA >= 1 && IB >= 1 && IA * NW * 64 == UA && IB * NW * 64 == UB, "tile / wave mismatch");
+  static_assert(IA + IB < 16, "loads in flight per stage must fit the wait counter field");
+  GMEM const u32x4* A;
+  GMEM const u32x4* B;
+  uint32_t a_off[IA], b_off[IB];   // unit offset of every unit this lane loads, at the first stage
+
+  __device__ __forceinline__ SplitRing(const Ctx& ctx, const GemmOp& op, const GemmSetup& g, int wave, int lane) {
+    A = reinterpret_cast<GMEM const u32x4*>(resolve(ctx, op.a, g.z, g.sid, 8));
+    B = reinterpret_cast<GMEM const u32x4*>(resolve(ctx, op.b, g.z, g.sid, 8));
+    const uint64_t mrows = uint64_t(1) << g.tm, nrows = uint64_t(1) << g.tn;
+    const uint64_t kb0 = uint64_t(blockIdx.z) << (op.n_k - 3);    // this split's first block of 8
+    const int kbt = op.ab_k_bits - 3;                                // blocks of 8 per row
+#pragma unroll
+    for (int i = 0; i < IA; i++) {
+      const int slot = (wave * IA + i) * 64 + lane;
+      const int r = slot >> 2, u = (slot & 3) ^ ((r >> 2) & 3);
+      const uint64_t rr = uint64_t(r) < mrows ? uint64_t(r) : 0;      // rows past a partial tile repeat row 0
+      const uint64_t row = (g.h << op.n_m) | (g.tile_m << g.tm) | rr;
+      a_off[i] = (uint32_t)((((row << kbt) + kb0) << 2) + u);
+    }
+#pragma unroll
+    for (int i = 0; i < IB; i++) {
+      const int slot = (wave * IB + i) * 64 + lane;
+      const int c = slot >> 3, pv = slot & 7;
+      const int u = (pv & 4) | ((pv & 3) ^ ((c >> 1) & 3));
+      const uint64_t cc = uint64_t(c) < nrows ? uint64_t(c) : 0;
+      const uint64_t col = (g.h << op.n_n) | (g.tile_n << g.tn) | cc;
+      b_off[i] = (uint32_t)((((col << kbt) + kb0) << 3) + u);
+    }
+  }
+
+  // start the loads of stage `step` into ring buffer `buf`
+  __device__ __forceinline__ void issue(u32x4* lds, uint32_t step, int buf, int wave) const {
+    const uint32_t sa = step << 2, sb = step << 3;
+#pragma unroll
+    for (int i = 0; i < IA; i++)
+      __builtin_amdgcn_global_load_lds((GMEM const void*)(A + a_off[i] + sa),
+                                       (__attribute__((address_space(3))) void*)(&lds[buf * UNITS + (wave * IA + i) * 64]),
+                                       16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < IB; i++)
+      __builtin_amdgcn_global_load_lds((GMEM const void*)(B + b_off[i] + sb),
+                                       (__attribute__((address_space(3))) void*)(&lds[buf * UNITS + UA + (wave * IB + i) * 64]),
+                                       16, 0, 0);
+  }
+
+  // as DlRing::wait: this wave's loads of stage s are done once at most those
+  // of the `ahead` later stages in flight remain; then a plain barrier
+  __device__ __forceinline__ static void wait(int ahead) {
+    if (ahead >= 2 && NB >= 4) __builtin_amdgcn_s_waitcnt((2 * (IA + IB)) | (0x7 << 4) | (0xF << 8));
+    else if (ahead >= 1) __builtin_amdgcn_s_waitcnt((IA + IB) | (0x7 << 4) | (0xF << 8));
+    else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
+    __builtin_amdgcn_s_barrier();
+  }
+};
+
+// BF16x3 on pre-split operands: the 4M embedding on v_mfma_f32_32x32x16_bf16
+// (one op covers 8 complex summed values: lanes of half kg supply complex k
+// 4 kg .. 4 kg + 3 as (re, im) pairs), products hi*hi + hi*lo + lo*hi with
+// FP32 accumulation.  The operands arrive split (split_kernel) and stream
+// global -> LDS through the ring with no staging registers and no vector-ALU
+// work in the loop; lane c32 of a B read takes its column's pattern c32 & 1
+// (even real column: (re, -im) -> real part, odd: (im, re) -> imaginary).
+template <int BM, int BN, int WGM, int WGN, int OCC, int NB>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_bf16x3_dl(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  typedef SplitRing<BM, BN, NW, NB> Ring;
+  static_assert(NB == 3 || (NB == 4 && 2 * (Ring::IA + Ring::IB) < 16), "ring depth");
+  __shared__ __attribute__((aligned(16))) u32x4 lds[Ring::NBUF * Ring::UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Ring ring(ctx, op, g, wave, lane);
+  const uint32_t nsteps = 1u << (op.n_k - RK);                 // per split: at most 2^28
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int kg = lane >> 5, c32 = lane & 31, p = c32 & 1;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  // NB - 1 stages in flight; buffer indices rotate (no division in the loop)
+  for (int q = 0; q < NB - 1; q++)
+    if ((uint32_t)q < nsteps) ring.issue(lds, (uint32_t)q, q, wave);
+  int cur = 0, nxt = NB - 1;
+  for (uint32_t s = 0; s < nsteps; s++) {
+    const uint32_t left = nsteps - 1 - s;                      // stages after this one
+    Ring::wait(left >= (uint32_t)(NB - 2) ? NB - 2 : (int)left);
+    if (s + NB - 1 < nsteps) ring.issue(lds, s + NB - 1, nxt, wave);
+    nxt = nxt + 1 == NB ? 0 : nxt + 1;
+    const u32x4* L = &lds[cur * Ring::UNITS];
+    cur = cur + 1 == NB ? 0 : cur + 1;
+    u32x4 ah[FM], al[FM];
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+      const int row = wm * WM + i * 32 + c32;
+      ah[i] = L[sa_unit(row, 2 * kg)];
+      al[i] = L[sa_unit(row, 2 * kg + 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      const int col = wn * WN + j * 16 + (c32 >> 1);
+      const u32x4 bh = L[Ring::UA + sb_unit(col, p, 2 * kg)];
+      const u32x4 bl = L[Ring::UA + sb_unit(col, p, 2 * kg + 1)];
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                            __builtin_bit_cast(bf16x8, bh), acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                            __builtin_bit_cast(bf16x8, bl), acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                            __builtin_bit_cast(bf16x8, bh), acc[i][j], 0, 0, 0);
+    }
+  }
+  __syncthreads();                         // the epilogue reuses the LDS ring for its tables
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
+}
+
 // ------------------------------------------------------------------ split-K sum
 
 // Fixed-order sum of the split-K partial products of a GEMM (splits in
@@ -1199,6 +1397,9 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 7: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring (4M / 3M, summed bits lowest)
     case 8: *bm = 8; *bn = 7; return 0;     // 256 x 128 direct-to-LDS ring, 8 waves
     case 9: *bm = 7; *bn = 7; return 0;     // 128 x 128 direct-to-LDS ring, 3 (4M) / 4 (3M) waves per SIMD
+    case 10: *bm = 7; *bn = 7; return 0;    // 128 x 128 BF16x3 on pre-split operands (direct-to-LDS), 2 stages in flight
+    case 11: *bm = 8; *bn = 7; return 0;    // 256 x 128 BF16x3 on pre-split operands, 8 waves
+    case 12: *bm = 7; *bn = 7; return 0;    // 128 x 128 BF16x3 on pre-split operands, 3 stages in flight
     default: return -1;
   }
 }
@@ -1206,6 +1407,10 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
 bool gemm_tile_ok(const GemmOp& op, int tile, int prec) {
   int bm, bn;
   if (gemm_tile_bits(tile, &bm, &bn)) return false;
+  // pre-split operands run on their own kernel only
+  const bool split_tile = tile >= kSplitTile && tile < kSplitTile + kNumSplitTiles;
+  if (op.ab_split) return prec == TN_C64_BF16X3 && split_tile && op.n_k >= 3;
+  if (split_tile) return false;
   if (prec == TN_C128) return tile == kValuTile;
   if (tile < kNumTilesShared || tile == kValuTile) return true;
   if (prec == TN_C64_3M ? (tile != 7 && tile != 8 && tile != 9) : prec != TN_C64_4M) return false;
@@ -1235,6 +1440,9 @@ const char* gemm_kernel_name(const GemmOp& op, int prec) {
   }
   if (prec == TN_C64_BF16X3) {
     switch (op.tile) {
+      case kSplitTile: return "gemm_mfma_bf16x3_dl<128,128,2,2,2,3>";
+      case kSplitTile + 1: return "gemm_mfma_bf16x3_dl<256,128,4,2,2,3>";
+      case kSplitTile + 2: return "gemm_mfma_bf16x3_dl<128,128,2,2,1,4>";
       case 0: return "gemm_mfma_bf16x3<128,128,8,2,2>";
       case 1: return "gemm_mfma_bf16x3<64,128,8,1,2,1>";
       case 2: return "gemm_mfma_bf16x3<128,64,8,2,1>";
@@ -1341,6 +1549,9 @@ static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec,
   }
   if (prec == TN_C64_BF16X3) {
     switch (tile) {
+      case kSplitTile: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<128, 128, 2, 2, 2, 3>), grid, dim3(256), 0, s, ctx, op); break;
+      case kSplitTile + 1: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<256, 128, 4, 2, 2, 3>), grid, dim3(512), 0, s, ctx, op); break;
+      case kSplitTile + 2: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<128, 128, 2, 2, 1, 4>), grid, dim3(256), 0, s, ctx, op); break;
       case 0: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
       // the 64-row variants load twice as many elements per thread: one wave per SIMD
       case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;
@@ -1389,6 +1600,19 @@ hipError_t launch_accum(const Ctx& ctx, const AccumOp& op, bool f64, hipStream_t
 
 hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s) {
   hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, ctx, value, add);
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const Ctx& ctx, const SplitOp& in, hipStream_t s) {
+  SplitOp op = in;
+  if (op.n_k < 3 || op.n_rows + op.n_k > 40) return hipErrorInvalidValue;
+  make_runs(op.row_pos, op.n_rows, op.run_row);
+  make_runs(op.k_pos + 2, op.n_k - 2, op.run_khi);
+  for (int j = 0; j < 4; j++)
+    op.j_off[j] = ((j & 1) ? 1u << op.k_pos[0] : 0u) + ((j & 2) ? 1u << op.k_pos[1] : 0u);
+  const uint64_t threads = uint64_t(1) << (op.n_rows + op.n_k - 2);
+  dim3 grid(blocks_for(threads, 256), ctx.n_batch);
+  hipLaunchKernelGGL(split_kernel, grid, dim3(256), 0, s, ctx, op);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 //      that permuted layout directly (no separate transpose);
 //   7. arena offsets from buffer lifetimes (first fit).
 #include "plan.h"
+#include "smallk_rule.h"
 
 #include <algorithm>
 #include <cmath>
@@ -347,6 +348,35 @@ static bool pick_swap(int kc, const std::vector<int>& M, const std::vector<int>&
 // Classes are derived from the operand and output bit sets.
 // Longest summed range one matrix-core accumulator covers (log2).
 constexpr int kMaxSplitSumBits = 13;
+// Smallest BF16x3 matrix-core contraction (log2 complex multiply-adds) whose
+// operands are split into bf16 planes once, before the GEMM, instead of in
+// every block that loads a panel: the split pass reads each operand once and
+// writes 8 (A) or 16 (B) bytes per element.
+constexpr int kMinPresplitBits = 28;
+
+static void push(Prog& prog, Op op);
+
+// The split of one operand of a BF16x3 GEMM (see SplitOp): rows = the free
+// bits (positions `fpos`), then the batch bits (`hpos`); summed bits `kpos`.
+static Op split_op(const Ref& src, const int8_t* fpos, int nf, const int8_t* hpos, int nh, const int8_t* kpos,
+                   int nk, int patterns, int conj, int dst_buf, int node, double bytes) {
+  Op o;
+  o.kind = OpKind::Split;
+  o.node = node;
+  SplitOp& t = o.split;
+  t.src = src;
+  t.dst = buf_ref(dst_buf);
+  t.n_rows = nf + nh;
+  t.n_k = nk;
+  t.patterns = patterns;
+  t.conj = conj;
+  for (int i = 0; i < nf; i++) t.row_pos[i] = fpos[i];
+  for (int i = 0; i < nh; i++) t.row_pos[nf + i] = hpos[i];
+  for (int i = 0; i < nk; i++) t.k_pos[i] = kpos[i];
+  o.flops = 0;
+  o.bytes = bytes;
+  return o;
+}
 
 static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0, int conj_a,
                         int conj_b, const Ref& cref, const Layout& Cl, bool accumulate,
@@ -426,6 +456,22 @@ static Op make_contract(const tn_plan_s* p, const Operand& A0, const Operand& B0
     }
     g.k_split_bits = ks > 0 ? ks : 0;
     if (ks > 0) g.part = buf_ref(prog.new_buf((int64_t)p->elem_bytes << (h + fa + fb + ks)));
+    // BF16x3: split both operands once into the planes the matrix-core kernel
+    // streams (the GEMM then reads them instead of A and B)
+    if (p->prec == TN_C64_BF16X3 && !gemm_smallk_ok(g) && k >= 3 && h + fa + fb + k >= kMinPresplitBits) {
+      const int ba = prog.new_buf(int64_t(8) << (h + fa + k));
+      const int bb = prog.new_buf(int64_t(16) << (h + fb + k));
+      push(prog, split_op(g.a, g.a_m, fa, g.a_h, h, g.a_k, k, 1, g.conj_a, ba, node,
+                          8.0 * (std::exp2(A.lay.n()) + std::exp2(h + fa + k))));
+      push(prog, split_op(g.b, g.b_n, fb, g.b_h, h, g.b_k, k, 2, g.conj_b, bb, node,
+                          8.0 * std::exp2(B.lay.n()) + 16.0 * std::exp2(h + fb + k)));
+      g.a = buf_ref(ba);
+      g.b = buf_ref(bb);
+      g.conj_a = 0;
+      g.conj_b = 0;
+      g.ab_split = 1;
+      g.ab_k_bits = k;
+    }
   } else {
     op.kind = OpKind::Row;
     RowOp& r = op.row;
@@ -490,6 +536,8 @@ static void push(Prog& prog, Op op) {
     prog.touch(op.accum.src, idx); prog.touch(op.accum.dst, idx);
   } else if (op.kind == OpKind::Permute) {
     prog.touch(op.perm.src, idx); prog.touch(op.perm.dst, idx);
+  } else if (op.kind == OpKind::Split) {
+    prog.touch(op.split.src, idx); prog.touch(op.split.dst, idx);
   }
   prog.ops.push_back(op);
   if (prog.ops.back().kind == OpKind::Row && prog.ops.back().row.k_split_bits > 0) {
@@ -653,6 +701,7 @@ static uint64_t allocate(Prog& prog) {
         break;
       case OpKind::Accum: fix(op.accum.src); fix(op.accum.dst); break;
       case OpKind::Permute: fix(op.perm.src); fix(op.perm.dst); break;
+      case OpKind::Split: fix(op.split.src); fix(op.split.dst); break;
       default: break;
     }
   }

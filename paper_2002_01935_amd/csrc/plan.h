@@ -13,19 +13,21 @@
 
 namespace tn {
 
-enum class OpKind { Row, RowReduce, Gemm, Accum, Permute, Fill, Counter };
+enum class OpKind { Row, RowReduce, Gemm, Accum, Permute, Fill, Counter, Split };
 
 enum KernelClass { kRow = 0, kSplitK = 1, kGemm = 2, kGemmSplitK = 3 };
 
 struct Op {
   Op() { std::memset(&row, 0, sizeof row); std::memset(&gemm, 0, sizeof gemm);
-         std::memset(&accum, 0, sizeof accum); std::memset(&perm, 0, sizeof perm); }
+         std::memset(&accum, 0, sizeof accum); std::memset(&perm, 0, sizeof perm);
+         std::memset(&split, 0, sizeof split); }
   OpKind kind = OpKind::Fill;
   int node = -1;          // tree node this op belongs to (reporting / tuning)
   RowOp row;
   GemmOp gemm;
   AccumOp accum;
   PermuteOp perm;
+  SplitOp split;
   int64_t fill_off = 0, fill_bytes = 0;   // Fill: arena range to zero
   int32_t fill_slot = -1;                 // Fill: pointer-table slot (bytes = fill_bytes) instead
   double flops = 0, bytes = 0;            // algorithmic, per slice

@@ -111,6 +111,32 @@ struct GemmOp {
   int32_t k_split_bits;
   int32_t c_split_shift;
   BitRuns run_a_s, run_b_s;
+  // BF16x3 on pre-split operands: a and b point to SplitOp outputs (planes in
+  // the canonical row layout, see SplitOp) instead of complex64 tensors, and
+  // conj_a / conj_b were applied by the split; ab_k_bits = log2 of the whole
+  // summed range (the row length of the planes, splits included)
+  int32_t ab_split;
+  int32_t ab_k_bits;
+};
+
+// A complex64 GEMM operand X[row][k] (rows = H then free bits, 2^n_rows of
+// them; 2^n_k summed values, k in the order of the GEMM's summed bits) split
+// into bf16 hi = RNE(x) and lo = RNE(x - hi) (re and im each; the source
+// conjugated first when conj), stored for the BF16x3 matrix-core kernel:
+// per row, per block of 8 summed values, 16-byte units of four (re, im)
+// bf16 pairs.  A operand (patterns 1): units hi(k 0-3), lo(k 0-3),
+// hi(k 4-7), lo(k 4-7).  B operand (patterns 2): those four units for the
+// (re, -im) pattern that forms the real part of a product, then for the
+// (im, re) pattern that forms the imaginary part.
+struct SplitOp {
+  Ref src, dst;
+  int32_t n_rows, n_k;
+  int32_t patterns;        // 1 (A operand) or 2 (B operand)
+  int32_t conj;
+  int8_t row_pos[kMaxBits];   // source position of row bit i (-1: absent)
+  int8_t k_pos[kMaxBits];     // source position of summed bit i
+  BitRuns run_row, run_khi;   // set at launch: row bits, summed bits from the third on
+  uint32_t j_off[4];          // set at launch: source offset of summed values 0..3
 };
 
 // Fixed-order FP64 accumulation of each in-flight slice's root into dst.
@@ -200,5 +226,6 @@ static_assert(alignof(RowOp) >= 4 && sizeof(RowOp) % 4 == 0, "RowOp layout");
 static_assert(alignof(GemmOp) >= 4 && sizeof(GemmOp) % 4 == 0, "GemmOp layout");
 static_assert(alignof(PermuteOp) >= 4 && sizeof(PermuteOp) % 4 == 0, "PermuteOp layout");
 static_assert(alignof(AccumOp) >= 4 && sizeof(AccumOp) % 4 == 0, "AccumOp layout");
+static_assert(alignof(SplitOp) >= 4 && sizeof(SplitOp) % 4 == 0, "SplitOp layout");
 
 }  // namespace tn

@@ -113,7 +113,7 @@ def test_row_staged_stores(oracle_lib, shape):
         assert rel(gpu_contract(net, TWO, precision=prec), ref) < TOLS[prec]
 
 
-TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3, 7, 8, 9], "c64_bf16x3": [0, 1, 2, 3]}
+TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3, 7, 8, 9], "c64_bf16x3": [0, 1, 2, 3, 10, 11, 12]}
 
 
 @pytest.mark.parametrize("prec", sorted(TILE_CASES))
@@ -241,6 +241,11 @@ def test_gemm_split_k(oracle_lib, prec):
     from paper_2002_01935_amd.binding import Plan
     cases = [(pairwise_network(*s, seed=31 + i), f"perm {s}") for i, s in enumerate(SPLIT_SHAPES)]
     cases += [(_canonical_pair(0, 7, 7, 12, seed=5), "canonical"), (_canonical_pair(1, 6, 7, 11, seed=6), "canonical h")]
+    if prec == "c64_bf16x3":
+        # at least 2^28 multiply-adds: operands split into bf16 planes by the
+        # split pass (scattered axes, batch bits), then split-K on the planes
+        cases += [(pairwise_network(0, 7, 8, 14, seed=77), "presplit perm"),
+                  (pairwise_network(2, 6, 7, 13, seed=78), "presplit perm h")]
     for net, name in cases:
         note("split-k", prec, name)
         plan = Plan(net, TWO, precision=prec, gemm_all_sizes=True)
