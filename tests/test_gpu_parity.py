@@ -322,3 +322,25 @@ def test_graph_replays_match_eager(oracle_lib, monkeypatch):
             y = (x @ x).sum()                      # eager work between the calls
             torch.cuda.synchronize()
             assert torch.isfinite(y)
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+def test_rank_simplified_tree(oracle_lib, prec):
+    """A tree searched on the rank-simplified network (Sec. 3.7: merges that
+    do not raise rank, then the finder's tree over the survivors) contracts
+    on the GPU to the oracle's value of the original network on its own
+    unsimplified tree: a hyperedge circuit (fSim as SWAP . diag) with open
+    qubits, sliced."""
+    from tn_inputs.simplify import compose, rank_simplify, structure_network
+    net = circuit_network(4, 5, 12, 5, 0b1011001110100101, open_qubits=(2, 9, 13), decompose="swap_diag")
+    simp = rank_simplify(net)
+    st = find_tree(structure_network(net, simp), seed=0, trials=4, slice_width=16)
+    tree = compose(simp, st)
+    sl = list(st.meta["sliced"])
+    plain = find_tree(net, seed=0, trials=4)
+    rnet = net if prec == "c128" else c64_leaves(net)
+    ref = oracle_lib.contract(rnet, plain)
+    note("rank-simplified", prec, "merges", len(simp.pairs), "sliced", len(sl))
+    got = gpu_sliced(net, tree, sliced=sl, precision=prec)
+    assert got.shape == ref.shape
+    assert rel(got, ref) < TOLS[prec]
