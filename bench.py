@@ -400,7 +400,8 @@ def node_bench(spec, precision, reps):
             best = (t, tbest)
     t, best = best
     print(json.dumps({"mode": "node", "shape_mnk": [m, n, k], "precision": precision, "kernel_class": node["kclass"],
-                      "kernel": best["kind"], "tile": t, "ms": round(best["ms"], 4),
+                      "kernel": best["kind"], "kernel_name": plan.nodes()[0].get("kernel"), "tile": t,
+                      "ms": round(best["ms"], 4),
                       "tflops": round(best["flops"] / best["ms"] / 1e9, 2),
                       "gbs": round(best["bytes"] / best["ms"] / 1e6, 1), "ms_per_tile": per_tile, "reps": reps}))
 

@@ -31,6 +31,8 @@ namespace tn {
 #define GMEM __attribute__((address_space(1)))
 #define CMEM __attribute__((address_space(4)))
 #define TN_WAVE_SYNC() __builtin_amdgcn_wave_barrier()
+// A value the same in every lane of the wavefront, made known to the compiler as such.
+#define TN_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
 
 #include "rowops.h"
 

@@ -210,10 +210,15 @@ extern "C" int tn_plan_node_info(tn_plan_t p, int32_t k, int32_t* kernel_class, 
 static const char* op_kernel_name(const tn_plan_s* p, const Op& op, int* tile) {
   *tile = -1;
   switch (op.kind) {
-    case OpKind::Row: return op.row.k_split_bits >= 0 ? "splitk_kernel" : "row_kernel";
+    case OpKind::Row: {
+      if (op.row.k_split_bits >= 0) return "splitk_kernel";
+      RowOp r = op.row;
+      prepare_row(r);
+      return row_stream_ok(r) ? "row_stream_kernel" : "row_kernel";
+    }
     case OpKind::RowReduce: return "reduce_kernel";
     case OpKind::Gemm:
-      if (gemm_smallk_ok(op.gemm)) return "gemm_smallk";
+      if (gemm_smallk_ok(op.gemm)) return smallk_kernel_name(op.gemm, p->prec);
       *tile = p->prec == TN_C128 ? kValuTile : op.gemm.tile;
       return gemm_kernel_name(op.gemm, p->prec);
     case OpKind::Accum: return "accum_kernel";

@@ -16,6 +16,20 @@ hipError_t launch_accum(const Ctx& ctx, const AccumOp& op, bool f64, hipStream_t
 hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s);
 hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s);
 hipError_t launch_split(const Ctx& ctx, const SplitOp& op, hipStream_t s);
+// Workgroups (of 4 wavefronts) along x of a persistent launch that needs
+// `waves` wavefronts per grid row, with gy grid rows: about
+// kStreamWavesPerCU wavefronts per compute unit over the whole grid.
+constexpr int kStreamWavesPerCU = 16;
+// Streaming row kernel: blocks of 64 rows per unit (1 or 2), and the store
+// mode for contiguous complex64 output blocks (1: coalesced pieces, 2: LDS
+// staging) by in-thread value count.  Measured on MI355X (ms per launch,
+// 1 / 2 blocks per unit): 2^26 x 16 outputs from one summed value: staging
+// 1.79 / 1.77, coalesced 2.00 / 2.01; 2^25 x 8 from two: staging 0.559 /
+// 0.537, coalesced 0.575 / 0.561; 2^28 x 4 from four: staging 3.63 / 3.64,
+// coalesced 3.45 / 3.29.
+constexpr int kRowStreamBlocks = 2;
+constexpr int kRowStreamMode(int nin) { return nin >= 8 ? 2 : 1; }
+unsigned stream_grid_x(uint64_t waves, unsigned gy);
 // log2 tile sizes of a gemm tile variant; -1 if unknown
 int gemm_tile_bits(int tile, int* bm, int* bn);
 // whether tile variant `tile` can run op at precision prec

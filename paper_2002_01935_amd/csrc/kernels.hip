@@ -25,6 +25,7 @@
 //   gemm_valu      tiled vector-ALU complex GEMM, used for complex128.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "kernels.h"
@@ -41,6 +42,8 @@ namespace tn {
 // Point where all lanes of a wavefront have passed the preceding LDS writes
 // (a wavefront runs its lanes together: only compiler reordering is fenced).
 #define TN_WAVE_SYNC() __builtin_amdgcn_wave_barrier()
+// A value the same in every lane of the wavefront, made known to the compiler as such.
+#define TN_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
 
 #include "rowops.h"
 
@@ -1317,6 +1320,21 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
 
 static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
+unsigned stream_grid_x(uint64_t waves, unsigned gy) {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int n = cus[dev].load(std::memory_order_relaxed);
+  if (n <= 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev].store(n, std::memory_order_relaxed);
+  }
+  const uint64_t want = uint64_t(n) * kStreamWavesPerCU / 4;      // 4 wavefronts per workgroup
+  const uint64_t per_y = want / gy > 0 ? want / gy : 1;
+  const uint64_t need = (waves + 3) / 4;
+  return (unsigned)(need < per_y ? need : per_y);
+}
+
 // Summed-range steps per batch of loads: row_ku(NIN), or the whole range when
 // it is shorter (log2 given in ubits).
 template <typename T, int NIN>
@@ -1339,9 +1357,52 @@ static void launch_row_u(bool splitk, dim3 grid, const Ctx& ctx, const RowOp& op
 #undef TN_ROW_LAUNCH
 }
 
+template <typename T, int NIN>
+static void launch_row_stream_n(const Ctx& ctx, const RowOp& op, hipStream_t s) {
+  const RowKOffsets ko = row_k_offsets(op);
+  const bool contiguous = op.stage_c && sizeof(T) == 4 && NIN >= 2;
+  const int rb = op.n_rows >= 7 ? kRowStreamBlocks : 1;
+  const uint64_t waves = (uint64_t(1) << (op.n_rows - 6)) / rb;
+  const dim3 grid(stream_grid_x(waves, (unsigned)ctx.n_batch), ctx.n_batch);
+  auto go = [&](auto kn) {
+    constexpr int KN = decltype(kn)::value;
+    auto with_rb = [&](auto mode) {
+      constexpr int M = decltype(mode)::value;
+      if (rb == 2) hipLaunchKernelGGL((row_stream_kernel<T, NIN, KN, M, 2>), grid, dim3(kRowThreads), 0, s, ctx, op, ko);
+      else hipLaunchKernelGGL((row_stream_kernel<T, NIN, KN, M, 1>), grid, dim3(kRowThreads), 0, s, ctx, op, ko);
+    };
+    if constexpr (sizeof(T) == 4 && NIN >= 2)
+      if (contiguous) {
+        if (kRowStreamMode(NIN) == 1) with_rb(std::integral_constant<int, 1>());
+        else with_rb(std::integral_constant<int, 2>());
+        return;
+      }
+    with_rb(std::integral_constant<int, 0>());
+  };
+  if (op.n_k == 0) go(std::integral_constant<int, 1>());
+  else if constexpr (NIN <= 8) {
+    if (op.n_k == 1) go(std::integral_constant<int, 2>());
+    else if constexpr (NIN <= 4) go(std::integral_constant<int, 4>());
+  }
+}
+
+template <typename T>
+static hipError_t launch_row_stream(const Ctx& ctx, const RowOp& op, hipStream_t s) {
+  switch (op.n_in) {
+    case 0: launch_row_stream_n<T, 1>(ctx, op, s); break;
+    case 1: launch_row_stream_n<T, 2>(ctx, op, s); break;
+    case 2: launch_row_stream_n<T, 4>(ctx, op, s); break;
+    case 3: launch_row_stream_n<T, 8>(ctx, op, s); break;
+    case 4: launch_row_stream_n<T, 16>(ctx, op, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_row_t(const Ctx& ctx, const RowOp& op, hipStream_t s) {
   const bool splitk = op.k_split_bits >= 0;
+  if (row_stream_ok(op)) return launch_row_stream<T>(ctx, op, s);
   uint64_t units;
   int ubits;
   if (splitk) {

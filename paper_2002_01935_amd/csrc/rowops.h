@@ -169,6 +169,21 @@ __device__ __forceinline__ uint32_t deposit_runs32(uint32_t v, const BitRuns& R)
   return off;
 }
 
+// The same for an index that is uniform over the wavefront, one run per pass
+// of a loop that is kept rolled: the run table stays in memory (scalar loads
+// at each use) instead of holding scalar registers across an enclosing loop.
+__device__ __forceinline__ uint32_t deposit_runs_u(uint32_t v, const BitRuns& R) {
+  uint32_t off = 0;
+  const int n = R.n;
+#pragma unroll 1
+  for (int i = 0; i < n; i++) {
+    const uint32_t w = R.r[i];
+    const uint32_t src = w & 0xFF, dst = (w >> 8) & 0xFF, len = w >> 16;
+    off |= ((v >> src) & (~0u >> (32 - len))) << dst;
+  }
+  return off;
+}
+
 // Offset change of a summed-bit walk from counter value c to c + 1, from the
 // op's carry table (the carry bit is clamped to the walk's n bits, so the
 // last step of a walk is harmless and needs no guard).
@@ -194,6 +209,58 @@ __device__ __forceinline__ uint64_t step_delta(uint64_t c, const int8_t* pos, in
 // parameter chosen on the host: the range is a power of two, so no step is
 // ever predicated and the compiler keeps all of a chunk's loads in flight).
 constexpr int row_ku(int nin) { return nin <= 2 ? 8 : (nin <= 4 ? 4 : 2); }
+
+// Stores of one row's in-thread outputs (C + oc + in_off_c[j]).  STAGE: the
+// wavefront's 64 consecutive rows form one contiguous block of 64 * NIN values
+// (prepare_row's stage_c); each lane puts its NIN values into the wavefront's
+// LDS area (rows padded by 16 bytes against bank conflicts) and the wavefront
+// then stores the block in 1 KiB pieces (16 bytes per lane), instead of
+// 16-byte pieces at a row stride that touch 64 cache lines per store.
+// blk_c: offset in C of the wavefront's first row (used by STAGE only).
+template <typename T, int NIN, bool STAGE, typename V>
+__device__ __forceinline__ void row_store(const RowOp& op, GMEM V* Cp, uint32_t oc, uint32_t blk_c, const V (&acc)[NIN],
+                                          uint32_t tid) {
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  if constexpr (STAGE && NIN >= 2) {
+    constexpr int RS = NIN * 8 + 16;                        // bytes per staged row
+    __shared__ __attribute__((aligned(16))) char stage[kRowThreads / 64][64 * RS];
+    const int lane = tid & 63;
+    char* S = &stage[tid >> 6][0];
+#pragma unroll
+    for (int j = 0; j < NIN; j += 2) {
+      t4 w;
+      w[0] = acc[j].x;
+      w[1] = acc[j].y;
+      w[2] = acc[j + 1].x;
+      w[3] = acc[j + 1].y;
+      *reinterpret_cast<t4*>(S + lane * RS + j * 8) = w;
+    }
+    // one wavefront's area only: its LDS accesses are performed in order
+    TN_WAVE_SYNC();
+    GMEM t4* D = reinterpret_cast<GMEM t4*>(Cp + blk_c);
+#pragma unroll
+    for (int t = 0; t < NIN / 2; t++) {
+      const int c = lane + 64 * t;                           // 16-byte piece of the block
+      D[c] = *reinterpret_cast<const t4*>(S + (c / (NIN / 2)) * RS + (c % (NIN / 2)) * 16);
+    }
+    // the next row's LDS writes follow this wavefront's reads
+    TN_WAVE_SYNC();
+  } else if (NIN >= 2 && op.pair_c) {
+    // in-thread values j and j + 1 are adjacent in C
+#pragma unroll
+    for (int j = 0; j < NIN; j += 2) {
+      t4 w;
+      w[0] = acc[j].x;
+      w[1] = acc[j].y;
+      w[2] = acc[j + 1].x;
+      w[3] = acc[j + 1].y;
+      *reinterpret_cast<GMEM t4*>(Cp + oc + op.in_off_c[j]) = w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NIN; j++) st(Cp + oc + op.in_off_c[j], acc[j]);
+  }
+}
 
 // One thread per row; the summed bits are walked in order with their A / B
 // offsets advanced as masked counters, and a batch of A loads (and the B
@@ -296,47 +363,171 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(Ctx ctx, RowOp op) {
       acc[j].y += o.y;
     }
   }
-  if constexpr (STAGE && NIN >= 2) {
-    // The wavefront's output is one contiguous block of 64 * NIN values:
-    // each lane puts its NIN values into the wavefront's LDS area (rows
-    // padded by 16 bytes against bank conflicts) and the wavefront then
-    // stores the block in 1 KiB pieces (16 bytes per lane), instead of
-    // 16-byte pieces at a row stride that touch 64 cache lines per store.
-    constexpr int RS = NIN * 8 + 16;                        // bytes per staged row
-    __shared__ __attribute__((aligned(16))) char stage[kRowThreads / 64][64 * RS];
-    const int lane = tid & 63;
-    char* S = &stage[tid >> 6][0];
+  row_store<T, NIN, STAGE>(op, Cp, oc, STAGE ? deposit_runs32(r32 & ~63u, op.run_c) : 0u, acc, tid);
+}
+
+// Walk of a persistent wavefront over the units first, first + step, ... <
+// count, with two register sets in turn so that no value is copied between
+// them: the loads into one set are issued before the stores of the unit held
+// by the other (past the last unit, a set reloads its own unit: in bounds,
+// unused).  Vector memory operations complete in issue order, so a load
+// issued after a batch of stores could only be consumed once those stores had
+// completed; this way the stores stay in flight.  The first unit is peeled
+// off so that every entry to the loop sees the same operations in flight (one
+// set's loads, then the other set's stores): the wait count before each body
+// is then the same on every pass.
+template <typename S, typename L, typename Bd>
+__device__ __forceinline__ void stream_walk(uint32_t first, uint32_t step, uint32_t count, S& s0, S& s1, L&& load,
+                                            Bd&& body) {
+  load(s0, first);
+  uint32_t nx = first + step;                     // unit held in s1
+  load(s1, nx < count ? nx : first);
+  body(s0, first);
+  while (nx < count) {
+    const uint32_t n2 = nx + step;
+    load(s0, n2 < count ? n2 : nx);
+    body(s1, nx);
+    if (n2 >= count) break;
+    const uint32_t n3 = n2 + step;
+    load(s1, n3 < count ? n3 : n2);
+    body(s0, n2);
+    nx = n3;
+  }
+}
+
+// Streaming row kernel for ops whose B has no row bit (the same small tensor
+// applied to every row) and whose summed range is at most four values: such
+// ops write NIN outputs per value of A they read and are bound by the HBM
+// write of C.  Persistent wavefronts walk units of RB blocks of 64
+// consecutive rows (stream_walk: the next unit's A values are loaded before
+// the current unit's stores).  Stores (MODE):
+//   0: each lane takes one row of a block and stores its NIN values;
+//   1 (complex64, the block one contiguous run of C with the in-thread
+//      values lowest, prepare_row's stage_c): store t of a lane writes
+//      16-byte piece lane + 64 t of the block, values 2 p and 2 p + 1
+//      (p = lane mod NIN / 2) of row lane / (NIN / 2) + t * 128 / NIN, so
+//      that every store covers 1 KiB of C with no exchange between lanes;
+//      each lane loads the A values of its NIN / 2 rows and keeps its pair's
+//      B values;
+//   2 (the same layouts): one row per lane, the block staged through LDS
+//      and stored in 1 KiB pieces (row_store).
+// The sum over k runs in index order, as in row_kernel.
+template <typename T, int NIN, int KN, int MODE, int RB>
+__global__ __launch_bounds__(kRowThreads) void row_stream_kernel(Ctx ctx, RowOp op, RowKOffsets ko) {
+  using V = typename C2<T>::t;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  constexpr int WPB = kRowThreads / 64;
+  static_assert(MODE == 0 || (sizeof(T) == 4 && NIN >= 2), "coalesced pieces are complex64 pairs");
+  const int z = blockIdx.y;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63;
+  // uniform over the wavefront (the compiler cannot tell by itself): the
+  // block offsets below are then scalar work
+  const uint32_t wave = TN_UNIFORM(blockIdx.x * WPB + (tid >> 6));
+  const uint32_t nwave = gridDim.x * WPB;
+  const uint32_t units = 1u << (op.n_rows - 6) >> (RB == 2 ? 1 : 0);
+  if (wave >= units) return;
+  const int eb = sizeof(V);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb));
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb));
+  GMEM V* Cp = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb));
+  if constexpr (MODE == 1) {
+    constexpr int H = NIN / 2;                    // 16-byte pieces per row
+    const uint32_t p = lane % H;
+    V b0[KN], b1[KN];
 #pragma unroll
-    for (int j = 0; j < NIN; j += 2) {
-      t4 w;
-      w[0] = acc[j].x;
-      w[1] = acc[j].y;
-      w[2] = acc[j + 1].x;
-      w[3] = acc[j + 1].y;
-      *reinterpret_cast<t4*>(S + lane * RS + j * 8) = w;
+    for (int k = 0; k < KN; k++) {
+      b0[k] = conjv(ld(B + op.in_off_b[2 * p] + ko.b[k]), op.conj_b);
+      b1[k] = conjv(ld(B + op.in_off_b[2 * p + 1] + ko.b[k]), op.conj_b);
     }
-    // one wavefront's area only: its LDS accesses are performed in order
-    TN_WAVE_SYNC();
-    GMEM t4* D = reinterpret_cast<GMEM t4*>(Cp + deposit_runs32(r32 & ~63u, op.run_c));
+    // offsets in A of the lane's rows within a block
+    uint32_t la[H];
 #pragma unroll
-    for (int t = 0; t < NIN / 2; t++) {
-      const int c = lane + 64 * t;                           // 16-byte piece of the block
-      D[c] = *reinterpret_cast<const t4*>(S + (c / (NIN / 2)) * RS + (c % (NIN / 2)) * 16);
-    }
-  } else if (NIN >= 2 && op.pair_c) {
-    // in-thread values j and j + 1 are adjacent in C
+    for (int t = 0; t < H; t++) la[t] = deposit_runs32(lane / H + t * (64 / H), op.run_a);
+    struct Set {
+      V a[RB][H][KN];
+    };
+    Set s0, s1;
+    stream_walk(
+        wave, nwave, units, s0, s1,
+        [&](Set& s, uint32_t u) {
 #pragma unroll
-    for (int j = 0; j < NIN; j += 2) {
-      t4 w;
-      w[0] = acc[j].x;
-      w[1] = acc[j].y;
-      w[2] = acc[j + 1].x;
-      w[3] = acc[j + 1].y;
-      *reinterpret_cast<GMEM t4*>(Cp + oc + inc[j]) = w;
-    }
+          for (int r = 0; r < RB; r++) {
+            GMEM const V* Ab = A + deposit_runs_u((u * RB + r) << 6, op.run_a);
+#pragma unroll
+            for (int t = 0; t < H; t++)
+#pragma unroll
+              for (int k = 0; k < KN; k++) s.a[r][t][k] = ld(Ab + la[t] + ko.a[k]);
+          }
+        },
+        [&](const Set& s, uint32_t u) {
+#pragma unroll
+          for (int r = 0; r < RB; r++) {
+            GMEM t4* D = reinterpret_cast<GMEM t4*>(Cp + deposit_runs_u((u * RB + r) << 6, op.run_c));
+#pragma unroll
+            for (int t = 0; t < H; t++) {
+              V u0, u1;
+              u0.x = u0.y = u1.x = u1.y = 0;
+#pragma unroll
+              for (int k = 0; k < KN; k++) {
+                const V a = conjv(s.a[r][t][k], op.conj_a);
+                u0 = cfma(u0, a, b0[k]);
+                u1 = cfma(u1, a, b1[k]);
+              }
+              t4 w;
+              w[0] = u0.x;
+              w[1] = u0.y;
+              w[2] = u1.x;
+              w[3] = u1.y;
+              D[lane + 64 * t] = w;
+            }
+          }
+        });
   } else {
+    // B's values are the same for every lane: scalar loads, once
+    CMEM const V* Bc = reinterpret_cast<CMEM const V*>(reinterpret_cast<uintptr_t>(B));
+    V bv[NIN][KN];
 #pragma unroll
-    for (int j = 0; j < NIN; j++) st(Cp + oc + inc[j], acc[j]);
+    for (int j = 0; j < NIN; j++)
+#pragma unroll
+      for (int k = 0; k < KN; k++) bv[j][k] = conjv(ldc(Bc + op.in_off_b[j] + ko.b[k]), op.conj_b);
+    // a row's offsets: deposit of its block's first row (uniform) + of its lane
+    const uint32_t la = deposit_runs32(lane, op.run_a), lc = deposit_runs32(lane, op.run_c);
+    struct Set {
+      V a[RB][KN];
+    };
+    Set s0, s1;
+    stream_walk(
+        wave, nwave, units, s0, s1,
+        [&](Set& s, uint32_t u) {
+#pragma unroll
+          for (int r = 0; r < RB; r++) {
+            const uint32_t oa = deposit_runs_u((u * RB + r) << 6, op.run_a) + la;
+#pragma unroll
+            for (int k = 0; k < KN; k++) s.a[r][k] = ld(A + oa + ko.a[k]);
+          }
+        },
+        [&](const Set& s, uint32_t u) {
+#pragma unroll
+          for (int r = 0; r < RB; r++) {
+            V sum[NIN];
+#pragma unroll
+            for (int j = 0; j < NIN; j++) {
+              sum[j].x = 0;
+              sum[j].y = 0;
+            }
+#pragma unroll
+            for (int k = 0; k < KN; k++) {
+              const V a = conjv(s.a[r][k], op.conj_a);
+#pragma unroll
+              for (int j = 0; j < NIN; j++) sum[j] = cfma(sum[j], a, bv[j][k]);
+            }
+            const uint32_t bc = deposit_runs_u((u * RB + r) << 6, op.run_c);
+            row_store<T, NIN, MODE == 2>(op, Cp, bc + lc, bc, sum, tid);
+          }
+        });
   }
 }
 

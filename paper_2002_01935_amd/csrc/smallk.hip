@@ -7,11 +7,17 @@
 // the free side that holds C's lowest bit (consecutive lanes write consecutive
 // elements) and R indices of the other side: it loads its own K operand
 // values once and, per output, the other operand's K values, which all lanes
-// of a wavefront share (one cached address).  The sum over k runs in index
-// order in the storage precision (FP32 for complex64, FP64 for complex128).
+// of a wavefront share (one cached address).  Without accumulation into C
+// and with a fast side of at least 64 threads the streaming variant runs
+// instead (persistent wavefronts, the next unit's operands loaded before the
+// current unit's stores).  The sum over k runs in index order in the storage
+// precision (FP32 for complex64, FP64 for complex128).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/tn.h"
+#include "kernels.h"
 #include "smallk.h"
 
 namespace tn {
@@ -19,6 +25,8 @@ namespace tn {
 #define GMEM __attribute__((address_space(1)))
 #define CMEM __attribute__((address_space(4)))
 #define TN_WAVE_SYNC() __builtin_amdgcn_wave_barrier()
+// A value the same in every lane of the wavefront, made known to the compiler as such.
+#define TN_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
 
 #include "rowops.h"
 #include "smallk_kernel.h"
@@ -31,17 +39,23 @@ hipError_t launch_gemm_smallk(const Ctx& ctx, const GemmOp& in, int prec, hipStr
   if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return hipErrorInvalidValue;
   if (L.blocks > 0x7fffffffULL || L.gy > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)L.blocks, (unsigned)L.gy, 1);
-  if (prec == TN_C128) {
-    if (L.fastn) gemm_smallk<double, true, 1, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-    else gemm_smallk<double, false, 1, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-  } else if (L.pair) {
-    if (L.fastn) gemm_smallk<float, true, 2, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-    else gemm_smallk<float, false, 2, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-  } else {
-    if (L.fastn) gemm_smallk<float, true, 1, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-    else gemm_smallk<float, false, 1, R><<<grid, 256, 0, s>>>(ctx, op, kt);
-  }
+  const dim3 sgrid(L.stream ? stream_grid_x(L.units, (unsigned)L.gy) : 1u, (unsigned)L.gy, 1);
+  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto stream) {
+    using T = decltype(t);
+    constexpr bool FN = decltype(fastn)::value;
+    constexpr int P = decltype(p)::value, KN = decltype(kn)::value;
+    if constexpr (decltype(stream)::value) gemm_smallk_stream<T, FN, P, KN><<<sgrid, 256, 0, s>>>(ctx, op, kt);
+    else gemm_smallk<T, FN, P, R, KN><<<grid, 256, 0, s>>>(ctx, op, kt);
+  });
   return hipGetLastError();
+}
+
+const char* smallk_kernel_name(const GemmOp& in, int prec) {
+  GemmOp op = in;
+  SmallkTables kt;
+  SmallkLaunch L;
+  if (!smallk_prepare(op, prec, 1, kt, L)) return "gemm_smallk";
+  return L.stream ? "gemm_smallk_stream" : "gemm_smallk";
 }
 
 }  // namespace tn

@@ -15,9 +15,12 @@ constexpr int kSmallkRows = 32;   // rows of the shared index per thread
 // of the thread's second own index (P = 2) in its operand (f1).
 struct SmallkTables {
   uint32_t kf[4], ks[4], si[32], ci[32], f1;
+  uint32_t dci[5];   // ci[i + 1] - ci[i] when i has t trailing ones (streaming variant)
 };
 
-template <typename T, bool FASTN, int P, int R>
+// KN = 2^n_k summed values (a template parameter: every load is issued
+// unconditionally, none waits behind a branch).
+template <typename T, bool FASTN, int P, int R, int KN>
 __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTables kt) {
   using V = typename C2<T>::t;
   static_assert(P == 1 || (P == 2 && sizeof(T) == 4), "paired stores are 16-byte complex64 pairs");
@@ -37,7 +40,6 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
   GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit_runs32(h, op.run_a_h);
   GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit_runs32(h, op.run_b_h);
   GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit_runs32(h, op.run_c_h);
-  const int K = 1 << op.n_k;
   GMEM const V* F = (FASTN ? B : A) + deposit_runs32(f, FASTN ? op.run_b_n : op.run_a_m);
   GMEM const V* S = (FASTN ? A : B) + deposit_runs32(uint32_t(s0), FASTN ? op.run_a_m : op.run_b_n);
   GMEM V* Cr = C + deposit_runs32(f, FASTN ? op.run_c_n : op.run_c_m) +
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
   for (int p = 0; p < P; p++)
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < K) fv[p][k] = conjv(ld(F + (p ? kt.f1 : 0u) + kt.kf[k]), cjf);
+      if (k < KN) fv[p][k] = conjv(ld(F + (p ? kt.f1 : 0u) + kt.kf[k]), cjf);
 #pragma unroll
   for (int i = 0; i < R; i++) {
     V acc[P];
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
     }
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < K) {
+      if (k < KN) {
         const V sv = conjv(ld(S + kt.si[i] + kt.ks[k]), cjs);
 #pragma unroll
         for (int p = 0; p < P; p++) acc[p] = FASTN ? cfma(acc[p], sv, fv[p][k]) : cfma(acc[p], fv[p][k], sv);
@@ -90,6 +92,132 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
   }
 }
 
+// Streaming variant (no accumulation into C, and a fast side of at least 64
+// threads, so that the 64 lanes of a wavefront share their R rows):
+// persistent wavefronts walk units of 64 lanes x R rows.  Per unit a lane
+// loads its own operand's K values and one or two of the R x K values of the
+// other operand that the wavefront shares (lane l holds row l mod R, summed
+// value l / R, ...); the wavefront puts those into its LDS area and each row
+// reads its shared values back at one address for all lanes (a broadcast),
+// so a unit needs no vector memory loads between its stores.  The loads
+// of the wavefront's next unit are issued before the current unit's stores
+// (stream_walk).
+template <typename T, bool FASTN, int P, int KN>
+__global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, SmallkTables kt) {
+  using V = typename C2<T>::t;
+  static_assert(P == 1 || (P == 2 && sizeof(T) == 4), "paired stores are 16-byte complex64 pairs");
+  constexpr int R = kSmallkRows;
+  constexpr int LP = P == 2 ? 1 : 0;
+  constexpr int Q = (R * KN + 63) / 64;   // shared-operand values per lane and unit
+  const int nzh = ctx.n_batch;
+  const int z = blockIdx.y % nzh;
+  const uint32_t h = blockIdx.y / nzh;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int nf = FASTN ? op.n_n : op.n_m;
+  const int ns = FASTN ? op.n_m : op.n_n;
+  const int fbits = nf - LP - 6;                        // >= 0 (the launcher checks)
+  const uint32_t units = 1u << (fbits + ns - 5);        // R = 2^5 rows per unit
+  const uint32_t lane = threadIdx.x & 63;
+  // uniform over the wavefront (the compiler cannot tell by itself): the
+  // unit offsets below are then scalar work
+  const uint32_t wave = TN_UNIFORM(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const uint32_t nwave = gridDim.x * 4;
+  if (wave >= units) return;
+  const int eb = sizeof(V);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit_runs32(h, op.run_a_h);
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit_runs32(h, op.run_b_h);
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit_runs32(h, op.run_c_h);
+  GMEM const V* F = FASTN ? B : A;
+  GMEM const V* S = FASTN ? A : B;
+  const BitRuns& rf = FASTN ? op.run_b_n : op.run_a_m;
+  const BitRuns& rs = FASTN ? op.run_a_m : op.run_b_n;
+  const BitRuns& rcf = FASTN ? op.run_c_n : op.run_c_m;
+  const BitRuns& rcs = FASTN ? op.run_c_m : op.run_c_n;
+  const int cjf = FASTN ? op.conj_b : op.conj_a, cjs = FASTN ? op.conj_a : op.conj_b;
+  const uint32_t fmask = (1u << fbits) - 1;
+  // summed value of this lane's q-th shared load: k = (lane + 64 q) / R
+  uint32_t ksl[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const uint32_t k = ((lane + 64 * q) / R) % KN;
+    ksl[q] = k == 0 ? kt.ks[0] : (k == 1 ? kt.ks[1] : (k == 2 ? kt.ks[2] : kt.ks[3]));
+  }
+  // offsets split into the unit's part (uniform) and the lane's part: the
+  // lane's fast-side index bits, and the shared row its loads cover
+  const uint32_t lf = deposit_runs32(lane << LP, rf), lcf = deposit_runs32(lane << LP, rcf);
+  uint32_t ls[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) ls[q] = deposit_runs32((lane + 64 * q) & (R - 1), rs) + ksl[q];
+  struct Set {
+    V f[P][KN];
+    V s[Q];
+  };
+  auto load = [&](Set& st_, uint32_t u) {
+    GMEM const V* Fp = F + deposit_runs_u((u & fmask) << (6 + LP), rf) + lf;
+    GMEM const V* Sp = S + deposit_runs_u((u >> fbits) * R, rs);
+#pragma unroll
+    for (int p = 0; p < P; p++)
+#pragma unroll
+      for (int k = 0; k < KN; k++) st_.f[p][k] = ld(Fp + (p ? kt.f1 : 0u) + kt.kf[k]);
+#pragma unroll
+    for (int q = 0; q < Q; q++) st_.s[q] = ld(Sp + ls[q]);
+  };
+  // the wavefront's shared values of one unit: [64 Q] values, entry i + R k
+  // holding row i, summed value k
+  __shared__ __attribute__((aligned(16))) char bcast[4][64 * Q * sizeof(V)];
+  V* Sw = reinterpret_cast<V*>(&bcast[threadIdx.x >> 6][0]);
+  auto body = [&](const Set& st_, uint32_t u, auto aligned) {
+    GMEM V* Cr = C + (deposit_runs_u((u & fmask) << (6 + LP), rcf) + deposit_runs_u((u >> fbits) * R, rcs)) + lcf;
+#pragma unroll
+    for (int q = 0; q < Q; q++) Sw[lane + 64 * q] = st_.s[q];
+    // one wavefront's area only: its LDS accesses are performed in order
+    TN_WAVE_SYNC();
+    uint32_t ci = 0;                              // offset of row i in C (rows walked in order)
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      if (i) ci += kt.dci[__builtin_ctz(~uint32_t(i - 1))];
+      V acc[P];
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        acc[p].x = 0;
+        acc[p].y = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < KN; k++) {
+        const V s = conjv(Sw[i + R * k], cjs);
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          const V f = conjv(st_.f[p][k], cjf);
+          acc[p] = FASTN ? cfma(acc[p], s, f) : cfma(acc[p], f, s);
+        }
+      }
+      GMEM V* d = Cr + ci;
+      if constexpr (P == 2) {
+        if constexpr (decltype(aligned)::value) {
+          smallk_f4 v = {acc[0].x, acc[0].y, acc[1].x, acc[1].y};
+          *reinterpret_cast<GMEM smallk_f4*>(d) = v;
+        } else {
+          st(d, acc[0]);
+          st(d + 1, acc[1]);
+        }
+      } else {
+        st(d, acc[0]);
+      }
+    }
+    // the next unit's LDS writes follow this wavefront's reads
+    TN_WAVE_SYNC();
+  };
+  auto run = [&](auto aligned) {
+    Set s0, s1;
+    stream_walk(wave, nwave, units, s0, s1, load, [&](const Set& st_, uint32_t u) { body(st_, u, aligned); });
+  };
+  // the pair's offsets in C are multiples of two elements: 16-byte alignment
+  // of every store follows from C's own
+  if (P == 2 && (reinterpret_cast<uint64_t>(C) & 15) == 0) run(std::true_type());
+  else run(std::false_type());
+}
+
 // Offset of a small value v (its set bits among the first n of a position list).
 inline uint32_t deposit_small(uint32_t v, const int8_t* pos, int n) {
   uint32_t off = 0;
@@ -99,10 +227,12 @@ inline uint32_t deposit_small(uint32_t v, const int8_t* pos, int n) {
 }
 
 
-// Grid and variant of one launch.
+// Grid and variant of one launch: units = wavefronts per grid row of the
+// streaming variant (stream), blocks = workgroups per grid row of the other.
 struct SmallkLaunch {
-  bool fastn, pair;
-  uint64_t blocks, gy;
+  bool fastn, pair, stream;
+  int kn;
+  uint64_t blocks, gy, units;
 };
 
 // Host side of a launch: the op's position lists as runs, the offset tables
@@ -137,8 +267,34 @@ inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, 
     kt.ci[i] = deposit_small(i, s_c, ns);
   }
   kt.f1 = deposit_small(1, f_op, nf);
+  for (int t = 0; t < 5; t++) kt.dci[t] = kt.ci[1 << t] - kt.ci[(1 << t) - 1];   // i = 2^t - 1 -> 2^t
   const uint64_t threads = (uint64_t(1) << (nf + ns)) / R / (L.pair ? 2 : 1);
   L.blocks = (threads + 255) / 256;
   L.gy = uint64_t(n_batch) << op.n_h;
+  L.kn = 1 << op.n_k;
+  L.stream = !op.accumulate && nf - (L.pair ? 1 : 0) >= 6;
+  L.units = threads / 64;
   return true;
+}
+
+// Calls f(T(), fastn, p, kn, stream) with the launch's variant as
+// std::integral_constant / bool_constant values.
+template <class Fn>
+inline void smallk_dispatch(const SmallkLaunch& L, int prec, Fn&& f) {
+  auto with_kn = [&](auto t, auto fastn, auto p, auto stream) {
+    if (L.kn == 1) f(t, fastn, p, std::integral_constant<int, 1>(), stream);
+    else if (L.kn == 2) f(t, fastn, p, std::integral_constant<int, 2>(), stream);
+    else f(t, fastn, p, std::integral_constant<int, 4>(), stream);
+  };
+  auto with_stream = [&](auto t, auto fastn, auto p) {
+    if (L.stream) with_kn(t, fastn, p, std::true_type());
+    else with_kn(t, fastn, p, std::false_type());
+  };
+  auto with_fastn = [&](auto t, auto p) {
+    if (L.fastn) with_stream(t, std::true_type(), p);
+    else with_stream(t, std::false_type(), p);
+  };
+  if (prec == TN_C128) with_fastn(double(), std::integral_constant<int, 1>());
+  else if (L.pair) with_fastn(float(), std::integral_constant<int, 2>());
+  else with_fastn(float(), std::integral_constant<int, 1>());
 }

@@ -219,6 +219,32 @@ inline void prepare_row(RowOp& op) {
   op.stage_c = st ? 1 : 0;
 }
 
+// Whether a row op takes the streaming row kernel: row mode without
+// accumulation, no row bit in B (the same small tensor for every row), at
+// least one wavefront of rows, at most four summed values and at most 16 B
+// values per row (run_b as set by prepare_row).
+inline bool row_stream_ok(const RowOp& op) {
+  return op.k_split_bits < 0 && !op.accumulate && op.run_b.n == 0 && op.n_rows >= 6 && op.n_k <= 2 &&
+         (1 << (op.n_in + op.n_k)) <= 16;
+}
+
+// Offsets of the summed values k < 4 in A and in B (launch-time table of the
+// streaming row kernel).
+struct RowKOffsets {
+  uint32_t a[4], b[4];
+};
+
+inline RowKOffsets row_k_offsets(const RowOp& op) {
+  RowKOffsets ko{};
+  for (int k = 0; k < (1 << op.n_k) && k < 4; k++)
+    for (int i = 0; i < op.n_k; i++)
+      if ((k >> i) & 1) {
+        ko.a[k] += 1u << op.k_a[i];
+        ko.b[k] += 1u << op.k_b[i];
+      }
+  return ko;
+}
+
 // Device code reads the int8 position lists a dword at a time: every op
 // struct must be 4-byte aligned with a size that is a multiple of 4.
 static_assert(offsetof(Ref, slice_bit) % 4 == 0 && offsetof(Ref, slice_pos) % 4 == 0, "Ref layout");

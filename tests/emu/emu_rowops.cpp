@@ -6,13 +6,16 @@
 // whose lane sums need the cross-lane shuffle), and writes the root of each
 // requested slice.  Test infrastructure: used by tests/test_kernel_emulation.py.
 //
-// usage: emu_rowops NET.txt LEAVES.bin OUT.bin
+// usage: emu_rowops NET.txt LEAVES.bin OUT.bin [FLAGS]
 //   NET.txt: n_leaves n_idx n_out prec / ranks / leaf indices / dims / out / left / right /
 //            n_sliced sliced... / n_ids ids...
 //   LEAVES.bin: complex128 leaves, row-major; OUT.bin: complex128 roots (out order), one per id
+//   FLAGS: tn_options.flags of the plan (default 0)
 // exit code 3: the plan holds an op kind the emulator does not run (matrix-core GEMM)
 // exit code 4: a few-summed-values GEMM op its launch preparation refused
+#include <algorithm>
 #include <barrier>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -21,6 +24,7 @@
 #include <string>
 #include <thread>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "plan.h"
@@ -29,7 +33,7 @@
 struct float2 { float x, y; };
 struct double2 { double x, y; };
 struct Dim3 { unsigned x, y, z; };
-static thread_local Dim3 threadIdx, blockIdx, blockDim;
+static thread_local Dim3 threadIdx, blockIdx, blockDim, gridDim;
 #define __global__
 #define __device__
 #define __forceinline__ inline
@@ -41,6 +45,8 @@ static thread_local Dim3 threadIdx, blockIdx, blockDim;
 static std::barrier<>* g_wave_barrier = nullptr;
 // lanes of a wavefront run as host threads in lockstep at this point
 #define TN_WAVE_SYNC() g_wave_barrier->arrive_and_wait()
+// every lane holds the same value already
+#define TN_UNIFORM(x) (x)
 static double g_lane_value[64];
 template <typename T>
 static T __shfl_xor(T v, int mask, int) {
@@ -101,8 +107,102 @@ static void call_any(bool splitk, const Ctx& ctx, const RowOp& op, bool stage = 
   }
 }
 
+// Runs fn() for every wavefront of a grid of `blocks` x `gy` workgroups of
+// 256 threads, one wavefront at a time, its 64 lanes as host threads in
+// lockstep (the kernels' wavefront syncs are barriers among them).
+template <class Fn>
+static void run_waves(unsigned blocks, unsigned gy, Fn fn) {
+  std::barrier<> bar(64);
+  g_wave_barrier = &bar;
+  std::vector<std::thread> lanes;
+  for (int l = 0; l < 64; l++)
+    lanes.emplace_back([&, l] {
+      for (unsigned y = 0; y < gy; y++)
+        for (unsigned b = 0; b < blocks; b++)
+          for (unsigned w = 0; w < 4; w++) {
+            blockDim = {256, 1, 1};
+            gridDim = {blocks, gy, 1};
+            blockIdx = {b, y, 0};
+            threadIdx = {w * 64 + l, 0, 0};
+            fn();
+            bar.arrive_and_wait();
+          }
+    });
+  for (auto& t : lanes) t.join();
+}
+
+// The streaming row kernel in each of its store modes and unit sizes that
+// apply, on one workgroup (four persistent wavefronts walk all row blocks).
+template <typename T, int NIN>
+static void run_row_stream_n(const Ctx& ctx, const RowOp& op, int z) {
+  const RowKOffsets ko = row_k_offsets(op);
+  const bool contiguous = op.stage_c && sizeof(T) == 4 && NIN >= 2;
+  // every variant writes all of C: each one's result is checked against the
+  // first one's (a variant that misplaced a value would otherwise be hidden
+  // by the next one overwriting it)
+  const size_t n_c = (size_t(1) << (op.n_rows + op.n_in)) * 2;
+  const int64_t sid = slice_id(ctx, z);
+  T* Cv = reinterpret_cast<T*>(resolve(ctx, op.c, z, sid, sizeof(T) * 2));
+  std::vector<T> first;
+  auto go = [&](auto kn) {
+    constexpr int KN = decltype(kn)::value;
+    auto one = [&](auto mode, auto rb) {
+      constexpr int M = decltype(mode)::value, RB = decltype(rb)::value;
+      std::fill(Cv, Cv + n_c, T(12345));
+      run_waves(1, 1, [&] {
+        blockIdx.y = z;
+        row_stream_kernel<T, NIN, KN, M, RB>(ctx, op, ko);
+      });
+      if (first.empty()) {
+        first.assign(Cv, Cv + n_c);
+        return;
+      }
+      double scale = 0;
+      for (size_t i = 0; i < n_c; i++) scale = std::max(scale, std::abs((double)first[i]));
+      for (size_t i = 0; i < n_c; i++)
+        if (std::abs((double)Cv[i] - (double)first[i]) > 1e-6 * scale) {
+          fprintf(stderr, "streaming row variant mode %d rb %d differs at %zu\n", M, RB, i);
+          exit(5);
+        }
+    };
+    auto modes = [&](auto rb) {
+      if constexpr (sizeof(T) == 4 && NIN >= 2)
+        if (contiguous) {
+          one(std::integral_constant<int, 1>(), rb);
+          one(std::integral_constant<int, 2>(), rb);
+        }
+      one(std::integral_constant<int, 0>(), rb);
+    };
+    modes(std::integral_constant<int, 1>());
+    if (op.n_rows >= 7) modes(std::integral_constant<int, 2>());
+  };
+  if (op.n_k == 0) go(std::integral_constant<int, 1>());
+  else if constexpr (NIN <= 8) {
+    if (op.n_k == 1) go(std::integral_constant<int, 2>());
+    else if constexpr (NIN <= 4) go(std::integral_constant<int, 4>());
+  }
+}
+
+template <typename T>
+static void run_row_stream(const Ctx& ctx, const RowOp& op, int z) {
+  switch (op.n_in) {
+    case 0: run_row_stream_n<T, 1>(ctx, op, z); break;
+    case 1: run_row_stream_n<T, 2>(ctx, op, z); break;
+    case 2: run_row_stream_n<T, 4>(ctx, op, z); break;
+    case 3: run_row_stream_n<T, 8>(ctx, op, z); break;
+    default: run_row_stream_n<T, 16>(ctx, op, z); break;
+  }
+}
+
+static int g_stream_ops = 0;   // streaming launches run (reported on stderr)
+
 template <typename T>
 static void run_row(const Ctx& ctx, const RowOp& op, int z) {
+  if (row_stream_ok(op)) {
+    g_stream_ops++;
+    run_row_stream<T>(ctx, op, z);
+    return;
+  }
   const uint64_t rows = 1ull << op.n_rows;
   const unsigned nblk = (unsigned)((rows + kRowThreads - 1) / kRowThreads);
   if (staged(op, sizeof(T) * 2)) {
@@ -174,40 +274,39 @@ static void run_reduce(const Ctx& ctx, const RowOp& op, int z) {
   for (auto& t : lanes) t.join();
 }
 
-// One launch of the few-summed-values GEMM kernel: every (block, thread) in
-// turn (the kernel has no cross-lane step).
-template <typename T, bool FASTN, int P>
-static void run_smallk_variant(const Ctx& ctx, const GemmOp& op, const SmallkTables& kt, const SmallkLaunch& L) {
-  blockDim = {256, 1, 1};
-  for (uint64_t y = 0; y < L.gy; y++)
-    for (uint64_t x = 0; x < L.blocks; x++)
-      for (unsigned t = 0; t < 256; t++) {
-        blockIdx = {(unsigned)x, (unsigned)y, 0};
-        threadIdx = {t, 0, 0};
-        gemm_smallk<T, FASTN, P, kSmallkRows>(ctx, op, kt);
-      }
-}
-
+// One launch of the few-summed-values GEMM kernel, in the variant the
+// library's launcher picks: the plain kernel thread by thread (it has no
+// cross-lane step), the streaming one on one workgroup per grid row (four
+// persistent wavefronts walk all units).
 static bool run_smallk(const Ctx& ctx, const GemmOp& in, int prec) {
   GemmOp op = in;
   SmallkTables kt;
   SmallkLaunch L;
   if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return false;
-  if (prec == TN_C128) {
-    if (L.fastn) run_smallk_variant<double, true, 1>(ctx, op, kt, L);
-    else run_smallk_variant<double, false, 1>(ctx, op, kt, L);
-  } else if (L.pair) {
-    if (L.fastn) run_smallk_variant<float, true, 2>(ctx, op, kt, L);
-    else run_smallk_variant<float, false, 2>(ctx, op, kt, L);
-  } else {
-    if (L.fastn) run_smallk_variant<float, true, 1>(ctx, op, kt, L);
-    else run_smallk_variant<float, false, 1>(ctx, op, kt, L);
-  }
+  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto stream) {
+    using T = decltype(t);
+    constexpr bool FN = decltype(fastn)::value;
+    constexpr int P = decltype(p)::value, KN = decltype(kn)::value;
+    if constexpr (decltype(stream)::value) {
+      g_stream_ops++;
+      run_waves(1, (unsigned)L.gy, [&] { gemm_smallk_stream<T, FN, P, KN>(ctx, op, kt); });
+    } else {
+      blockDim = {256, 1, 1};
+      gridDim = {(unsigned)L.blocks, (unsigned)L.gy, 1};
+      for (uint64_t y = 0; y < L.gy; y++)
+        for (uint64_t x = 0; x < L.blocks; x++)
+          for (unsigned th = 0; th < 256; th++) {
+            blockIdx = {(unsigned)x, (unsigned)y, 0};
+            threadIdx = {th, 0, 0};
+            gemm_smallk<T, FN, P, kSmallkRows, KN>(ctx, op, kt);
+          }
+    }
+  });
   return true;
 }
 
 int main(int argc, char** argv) {
-  if (argc != 4) return 1;
+  if (argc != 4 && argc != 5) return 1;
   FILE* f = fopen(argv[1], "r");
   if (!f) return 1;
   int nl, nidx, nout, prec;
@@ -233,6 +332,7 @@ int main(int argc, char** argv) {
   for (int i = 0; i < nids; i++) { long x; fscanf(f, "%ld", &x); ids[i] = x; }
   fclose(f);
   p->opt.prec = (tn_precision)prec;
+  p->opt.flags = argc == 5 ? (uint32_t)strtoul(argv[4], nullptr, 0) : 0u;
   p->prec = p->opt.prec;
   p->elem_bytes = prec == TN_C128 ? 16 : 8;
   std::string err;
@@ -311,5 +411,6 @@ int main(int argc, char** argv) {
   }
   fclose(fo);
   delete p;
+  fprintf(stderr, "streaming launches: %d\n", g_stream_ops);
   return 0;
 }

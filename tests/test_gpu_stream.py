@@ -1,0 +1,69 @@
+"""The streaming bandwidth kernels on the GPU (row_stream_kernel: no row bit
+in B, at most four summed values; gemm_smallk_stream: a GEMM with at most
+four summed values whose fast side spans a wavefront) at sizes where every
+persistent wavefront walks several units (a ragged last pass included),
+against the oracle: complex64 within 1e-5 of the exact value of the same
+complex64 leaves (normwise and max-componentwise), complex128 within 1e-10.
+Each case asserts that the node ran on the streaming kernel."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import TOL_C64, TOL_C128, c64_leaves, check, gpu_sliced, note
+from tn_inputs.graphs import pairwise_network
+from tn_inputs.network import Network, Tree
+
+pytestmark = pytest.mark.gpu
+
+TWO = Tree(np.array([0], np.int32), np.array([1], np.int32))
+
+
+def _rows(m, n, k, seed):
+    """A(M, K) x B(N, K) -> C(M, N), output in index order: the in-thread
+    bits N lowest in C, the row bits M above them (contiguous row blocks)."""
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+    b = rng.normal(size=(2,) * (n + k)) + 1j * rng.normal(size=(2,) * (n + k))
+    return Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
+
+
+def _run(net, prec, kernel, oracle_lib, sliced=()):
+    from paper_2002_01935_amd.binding import Plan
+    plan = Plan(net, TWO, sliced=list(sliced), precision=prec)
+    names = [nd["kernel"] for nd in plan.nodes()]
+    note("stream", prec, kernel, names, "sliced", list(sliced))
+    assert names == [kernel], names
+    ref = oracle_lib.contract(net if prec == "c128" else c64_leaves(net), TWO)
+    got = gpu_sliced(net, TWO, sliced=list(sliced), precision=prec, plan=plan)
+    check(got.ravel(), ref.ravel(), TOL_C128 if prec == "c128" else TOL_C64, "stream", prec, kernel)
+
+
+# (m, n, k): 2^m rows, 2^n in-thread values, 2^k summed values; 2^(m - 7)
+# units of two 64-row blocks against 4096 wavefronts (16 per compute unit)
+ROWS = [(20, 4, 0), (21, 2, 2), (21, 3, 1), (22, 0, 1), (19, 1, 2), (13, 4, 0)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", ROWS)
+def test_row_stream(oracle_lib, shape, prec):
+    _run(_rows(*shape, seed=sum(shape)), prec, "row_stream_kernel", oracle_lib)
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+def test_row_stream_sliced(oracle_lib, prec):
+    """A summed index sliced: several slices in flight on the grid's second
+    dimension, each walked by the persistent wavefronts."""
+    net = _rows(20, 2, 2, seed=5)
+    _run(net, prec, "row_stream_kernel", oracle_lib, sliced=[20])
+
+
+# (h, m, n, k): GEMM class by default (h + m + n + k >= 25), random axis orders
+SMALLK = [(0, 12, 12, 1), (0, 13, 12, 0), (1, 11, 11, 2), (0, 12, 13, 2), (2, 10, 12, 1)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK)
+def test_smallk_stream(oracle_lib, shape, prec):
+    net = pairwise_network(*shape, seed=7 * sum(shape) + 1, dims=(2,))
+    _run(net, prec, "gemm_smallk_stream", oracle_lib)

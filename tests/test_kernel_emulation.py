@@ -37,7 +37,12 @@ def emu(tmp_path_factory):
     return out
 
 
-def run(emu, net, prec, sliced=(), ids=(0,), tmp=None):
+def run(emu, net, prec, sliced=(), ids=(0,), tmp=None, streams=None, gemm_all_sizes=False):
+    """Root values of the emulated plan; `streams`, a list, receives the
+    number of launches that took a streaming (persistent) kernel.
+    gemm_all_sizes: GEMM-shaped contractions of any size take the GEMM class
+    (the plan flag TN_FLAG_GEMM_ALL_SIZES), so that small test networks reach
+    the few-summed-values kernel."""
     d = tmp
     with open(os.path.join(d, "net.txt"), "w") as f:
         f.write(f"{net.n_leaves} {len(net.idx_dim)} {len(net.out_idx)} {PREC[prec]}\n")
@@ -51,11 +56,15 @@ def run(emu, net, prec, sliced=(), ids=(0,), tmp=None):
         for t in net.leaves:
             np.ascontiguousarray(t, dtype=np.complex128).tofile(f)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    r = subprocess.run([emu, os.path.join(d, "net.txt"), os.path.join(d, "leaves.bin"), os.path.join(d, "out.bin")],
-                       capture_output=True, text=True, env=env)
+    args = [emu, os.path.join(d, "net.txt"), os.path.join(d, "leaves.bin"), os.path.join(d, "out.bin")]
+    if gemm_all_sizes:
+        args.append("1")
+    r = subprocess.run(args, capture_output=True, text=True, env=env)
     if r.returncode == 3:
         return None
     assert r.returncode == 0, r.stderr[-2000:]
+    if streams is not None:
+        streams.append(int(r.stderr.split("streaming launches:")[1].split()[0]))
     return np.fromfile(os.path.join(d, "out.bin"), dtype=np.complex128)
 
 
@@ -95,7 +104,7 @@ def test_smallk_emulated(emu, oracle_lib, tmp_path, shape, prec):
     16-byte stores, batch bits and conjugation-free operands."""
     for seed in range(3):
         net = pairwise_network(*shape, seed=2000 + 31 * seed + sum(shape), dims=(2, 4))
-        got = run(emu, net, prec, tmp=str(tmp_path))
+        got = run(emu, net, prec, tmp=str(tmp_path), gemm_all_sizes=True)
         assert got is not None, "plan uses a matrix-core GEMM"
         ref = oracle_lib.contract(net, TWO).ravel()
         assert rel(got, ref) < TOL[prec], (shape, prec, seed)
@@ -138,3 +147,40 @@ def test_sliced_emulated(emu, oracle_lib, tmp_path, prec):
         assert rel(got.sum(axis=0), ref) < TOL[prec]
         for s in (0, d - 1):
             assert rel(got[s], oracle_lib.contract(net, TWO, sliced=sliced, slice_ids=[s]).ravel()) < TOL[prec]
+
+
+@pytest.mark.parametrize("shape", [(9, 1, 2), (10, 4, 0), (8, 2, 1), (11, 0, 2), (8, 3, 1), (6, 2, 0)])
+def test_stream_rows_emulated(emu, oracle_lib, tmp_path, shape):
+    """The streaming row kernel (no row bit in B, at most four summed values):
+    four persistent wavefronts walk every block of 64 rows, the next block's
+    A values loaded before the current stores; staged and plain stores."""
+    net = _canonical_rows(*shape, seed=3 + sum(shape))
+    streams = []
+    got = run(emu, net, "c64_4m", tmp=str(tmp_path), streams=streams)
+    assert streams[0] >= 1
+    assert rel(got, oracle_lib.contract(net, TWO).ravel()) < TOL["c64_4m"]
+    got = run(emu, net, "c128", tmp=str(tmp_path))
+    assert rel(got, oracle_lib.contract(net, TWO).ravel()) < TOL["c128"]
+
+
+# (h, m, n, k): few-summed-values GEMMs whose fast side spans a wavefront,
+# which take the streaming variant
+SMALLK_STREAM = [(0, 8, 7, 2), (0, 7, 9, 0), (1, 8, 6, 1), (2, 7, 7, 2), (0, 9, 5, 1)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK_STREAM)
+def test_smallk_stream_emulated(emu, oracle_lib, tmp_path, shape, prec):
+    """gemm_smallk_stream on the host: persistent wavefronts over units of 64
+    fast-side lanes x 32 rows, the shared operand's values broadcast through
+    LDS, random axis orders (either side fast, paired and single stores)."""
+    n_stream = 0
+    for seed in range(3):
+        net = pairwise_network(*shape, seed=4000 + 31 * seed + sum(shape), dims=(2,))
+        streams = []
+        got = run(emu, net, prec, tmp=str(tmp_path), streams=streams, gemm_all_sizes=True)
+        assert got is not None, "plan uses a matrix-core GEMM"
+        n_stream += streams[0]
+        ref = oracle_lib.contract(net, TWO).ravel()
+        assert rel(got, ref) < TOL[prec], (shape, prec, seed)
+    assert n_stream >= 1
