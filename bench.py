@@ -24,6 +24,11 @@ Printed as one JSON line:
               launch's rate in the FLOPs its matrix cores execute
   adjoint     forward and reverse pass on cfg4 (all 180 fSim leaf gradients),
               with the oracle's forward and gradient of one sub-slice beside it
+
+Other modes (one JSON line each): --node M,N,K [precision] [reps] (one
+pairwise node), --qaoa [N] [p] [streams], --sample [n], --adjoint
+[precision] (the cfg4 forward and reverse pass alone, for profiling),
+--copy-calibration, --summarize-rocprof DIR.
 """
 
 from __future__ import annotations
@@ -74,7 +79,8 @@ def measured_traffic(kernel, precision, workload, log2_hmnk):
     record (profiles/traffic_*.json: FETCH_SIZE + WRITE_SIZE, each scaled by
     a plain copy's reading), or None when no record matches this kernel,
     node and the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    safe = "".join(c if c.isalnum() or c == "_" else "_" for c in kernel).strip("_")
+    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -268,6 +274,13 @@ def summarize_rocprof(path):
             lv = [x for x in v if x >= 0.9 * max(v)]
             out.append(f"{k[:52]:52s} {gs:26s} {len(v):6d} {sum(v) / len(v):10.3f} {min(v):10.3f} "
                        f"{sum(v):10.1f} {sum(v) / total:6.1%} {len(lv):6d} {sum(lv) / len(lv):10.3f}")
+        fam = defaultdict(lambda: [0, 0.0])
+        for (k, g), v in trace.items():
+            f = fam[k.split("<")[0]]
+            f[0] += len(v)
+            f[1] += sum(v)
+        out.append("by kernel (all template arguments and grids): " + "; ".join(
+            f"{k} {n} calls {t:.1f} ms" for k, (n, t) in sorted(fam.items(), key=lambda kv: -kv[1][1])))
     if pmc:
         out.append("PMC counters (mean per dispatch, KiB for FETCH_SIZE / WRITE_SIZE):")
         agg = []
@@ -539,6 +552,15 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
         copy_calibration()
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--adjoint":
+        import numpy as np
+        import torch
+
+        from paper_2002_01935_amd.binding import Plan
+        from tn_inputs import configs
+        prec = sys.argv[2] if len(sys.argv) > 2 else "c64_4m"
+        print(json.dumps(adjoint_bench(prec, torch, np, Plan, configs)))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
