@@ -181,9 +181,11 @@ int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void
  * 9 = 128x128 at more waves per SIMD, all direct-to-LDS (operands whose
  * summed indices are their lowest axes); for TN_C64_BF16X3, on operands
  * split into bf16 planes beforehand, all direct-to-LDS: 10 = 128x128,
- * 11 = 256x128 (the default), 12 = 128x128 with three stages in flight (the
- * planner splits the operands of contractions of at least 2^28
- * multiply-adds, which then run on variants 10-12 only; the others take 0-4).  *n_set (may be NULL) receives the
+ * 11 = 256x128 (the default), 12 = 128x128 with three stages in flight,
+ * 13 = 256x128 with the next stage's fragments read during the current
+ * stage's matrix-core work (the planner splits the operands of contractions
+ * of at least 2^28 multiply-adds, which then run on variants 10-13 only; the
+ * others take 0-4).  *n_set (may be NULL) receives the
  * number of contractions changed.  TN_E_INVALID for an unknown variant.  Used to test
  * every variant and to reproduce a tuned plan.
  */

@@ -1186,6 +1186,104 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
 
+// The same products with the fragments of the next stage read from LDS while
+// the matrix cores work on the current one.  A ring of four stages: at stage
+// s the wave waits for stage s + 1's loads (s + 2 stays in flight), passes the
+// barrier (after which the buffer of stage s - 1, whose fragments every wave
+// read one stage earlier, is free) and starts the loads of stage s + 3 into
+// it; it then issues stage s's matrix-core ops column block by column block,
+// reading stage s + 1's B fragments of a block into the block's registers
+// right after the block's last op has used them, and stage s + 1's A
+// fragments after the last block.  The LDS read latency overlaps the matrix
+// cores' work and the next stage's barrier, and one register set holds the
+// fragments.
+template <int BM, int BN, int WGM, int WGN, int OCC>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_bf16x3_dlp(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN, NB = 4;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  typedef SplitRing<BM, BN, NW, NB> Ring;
+  static_assert(Ring::IA + Ring::IB < 16, "loads in flight per stage must fit the wait counter field");
+  __shared__ __attribute__((aligned(16))) u32x4 lds[NB * Ring::UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Ring ring(ctx, op, g, wave, lane);
+  const uint32_t nsteps = 1u << (op.n_k - RK);                 // per split: a power of two
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int kg = lane >> 5, c32 = lane & 31, p = c32 & 1;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  auto buf = [&](uint32_t s) { return &lds[(s & (NB - 1)) * Ring::UNITS]; };   // stage s's buffer
+  u32x4 ah[FM], al[FM], bh[FN], bl[FN];                        // fragments, refilled as they die
+  auto read_a = [&](uint32_t s) {
+    const u32x4* L = buf(s);
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+      const int row = wm * WM + i * 32 + c32;
+      ah[i] = L[sa_unit(row, 2 * kg)];
+      al[i] = L[sa_unit(row, 2 * kg + 1)];
+    }
+  };
+  auto read_b = [&](int j, uint32_t s) {
+    const u32x4* L = buf(s);
+    const int col = wn * WN + j * 16 + (c32 >> 1);
+    bh[j] = L[Ring::UA + sb_unit(col, p, 2 * kg)];
+    bl[j] = L[Ring::UA + sb_unit(col, p, 2 * kg + 1)];
+  };
+  auto mma = [&](int j) {
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                          __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                          __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                          __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+  };
+  // Every stage runs the same operations, so that the compiler's wait counts
+  // hold on every pass: past the last stage the loads fetch the last stage
+  // again (into a buffer no later read uses) and the reads re-read it.
+  const uint32_t last = nsteps - 1;
+  auto clamp = [&](uint32_t t) { return t < last ? t : last; };
+  for (int q = 0; q < NB - 1; q++) ring.issue(lds, clamp((uint32_t)q), q, wave);
+  Ring::wait(2);                                               // stage 0 loaded
+  read_a(0);
+#pragma unroll
+  for (int j = 0; j < FN; j++) read_b(j, 0);
+  for (uint32_t s = 0; s < nsteps; s++) {
+    Ring::wait(1);                                             // stage s + 1 loaded, s + 2 in flight
+    ring.issue(lds, clamp(s + 3), (s + 3) & (NB - 1), wave);
+    const uint32_t nx = clamp(s + 1);
+    // (scheduling barriers keep the compiler from reordering the blocks)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      mma(j);
+      read_b(j, nx);
+      if (j == FN - 1) read_a(nx);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  Ring::wait(0);                           // no load into the ring still in flight
+  __syncthreads();                         // the epilogue reuses the LDS ring for its tables
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
+}
+
 // ------------------------------------------------------------------ split-K sum
 
 // Fixed-order sum of the split-K partial products of a GEMM (splits in
@@ -1461,6 +1559,7 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 10: *bm = 7; *bn = 7; return 0;    // 128 x 128 BF16x3 on pre-split operands (direct-to-LDS), 2 stages in flight
     case 11: *bm = 8; *bn = 7; return 0;    // 256 x 128 BF16x3 on pre-split operands, 8 waves
     case 12: *bm = 7; *bn = 7; return 0;    // 128 x 128 BF16x3 on pre-split operands, 3 stages in flight
+    case 13: *bm = 8; *bn = 7; return 0;    // 256 x 128 BF16x3 on pre-split operands, next stage's fragments prefetched
     default: return -1;
   }
 }
@@ -1504,6 +1603,7 @@ const char* gemm_kernel_name(const GemmOp& op, int prec) {
       case kSplitTile: return "gemm_mfma_bf16x3_dl<128,128,2,2,2,3>";
       case kSplitTile + 1: return "gemm_mfma_bf16x3_dl<256,128,4,2,2,3>";
       case kSplitTile + 2: return "gemm_mfma_bf16x3_dl<128,128,2,2,1,4>";
+      case kSplitTile + 3: return "gemm_mfma_bf16x3_dlp<256,128,4,2,2>";
       case 0: return "gemm_mfma_bf16x3<128,128,8,2,2>";
       case 1: return "gemm_mfma_bf16x3<64,128,8,1,2,1>";
       case 2: return "gemm_mfma_bf16x3<128,64,8,2,1>";
@@ -1613,6 +1713,7 @@ static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec,
       case kSplitTile: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<128, 128, 2, 2, 2, 3>), grid, dim3(256), 0, s, ctx, op); break;
       case kSplitTile + 1: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<256, 128, 4, 2, 2, 3>), grid, dim3(512), 0, s, ctx, op); break;
       case kSplitTile + 2: hipLaunchKernelGGL((gemm_mfma_bf16x3_dl<128, 128, 2, 2, 1, 4>), grid, dim3(256), 0, s, ctx, op); break;
+      case kSplitTile + 3: hipLaunchKernelGGL((gemm_mfma_bf16x3_dlp<256, 128, 4, 2, 2>), grid, dim3(512), 0, s, ctx, op); break;
       case 0: hipLaunchKernelGGL((gemm_mfma_bf16x3<128, 128, 8, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
       // the 64-row variants load twice as many elements per thread: one wave per SIMD
       case 1: hipLaunchKernelGGL((gemm_mfma_bf16x3<64, 128, 8, 1, 2, 1>), grid, dim3(128), 0, s, ctx, op); break;

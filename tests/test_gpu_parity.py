@@ -113,7 +113,7 @@ def test_row_staged_stores(oracle_lib, shape):
         assert rel(gpu_contract(net, TWO, precision=prec), ref) < TOLS[prec]
 
 
-TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3, 7, 8, 9], "c64_bf16x3": [0, 1, 2, 3, 10, 11, 12]}
+TILE_CASES = {"c64_4m": [0, 1, 2, 3, 5, 6, 7, 8, 9], "c64_3m": [0, 1, 2, 3, 7, 8, 9], "c64_bf16x3": [0, 1, 2, 3, 10, 11, 12, 13]}
 
 
 @pytest.mark.parametrize("prec", sorted(TILE_CASES))
@@ -136,6 +136,35 @@ def test_every_tile_variant(oracle_lib, prec):
             note("tile", prec, t, "net", ni, "changed", changed)
             got = gpu_sliced(net, tree, sliced=sl, precision=prec, plan=plan)
             assert rel(got, ref) < TOLS[prec], (prec, t, ni)
+
+
+# (h, m, n, k) of 2^28 multiply-adds (operands split into bf16 planes before
+# the GEMM): one stage of 8 summed values, two stages, many; batch bits;
+# canonical and scattered axes
+PRESPLIT = [("canonical", (0, 10, 10, 8)), ("canonical two stages", (0, 12, 12, 4)),
+            ("canonical one stage", (0, 12, 13, 3)), ("canonical h", (2, 9, 9, 8)), ("scattered", (0, 10, 9, 9)),
+            ("scattered h", (1, 9, 10, 8))]
+
+
+def test_presplit_tile_variants(oracle_lib):
+    """Every BF16x3 variant on pre-split operands (10-13) pinned with
+    tn_plan_set_tile, against the oracle, within the BF16x3 bound."""
+    from paper_2002_01935_amd.binding import Plan
+    for i, (name, shp) in enumerate(PRESPLIT):
+        net = (_canonical_pair(*shp, seed=90 + i) if name.startswith("canonical")
+               else pairwise_network(*shp, seed=90 + i, dims=(2,)))
+        ref = oracle_lib.contract(net, TWO)
+        for t in (10, 11, 12, 13):
+            plan = Plan(net, TWO, precision="c64_bf16x3")
+            # the variants on pre-split planes are the only ones such a node takes
+            assert plan.nodes()[0]["kernel"].startswith("gemm_mfma_bf16x3_dl"), name
+            plan.set_tile(t)
+            assert plan.nodes()[0]["tile"] == t, (name, t)
+            note("presplit", name, shp, "tile", t, plan.nodes()[0]["kernel"])
+            got = gpu_sliced(net, TWO, precision="c64_bf16x3", plan=plan)
+            e = rel(got, ref)
+            note("presplit", name, "tile", t, "rel err %.3e" % e)
+            assert e < TOL_BF16X3, (name, t, e)
 
 
 BACK = {"c64_4m": TOL_BACKWARD_C64, "c64_3m": TOL_BACKWARD_C64, "c64_bf16x3": TOL_BACKWARD_BF16X3}
