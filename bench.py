@@ -394,7 +394,7 @@ def node_bench(spec, precision, reps):
     # variant that applies is timed here instead
     per_tile = {}
     best = None
-    for t in (range(14) if node["kclass"].startswith("gemm") else [0]):
+    for t in (range(15) if node["kclass"].startswith("gemm") else [0]):
         if t == 4 or (t and plan.set_tile(t) == 0 and t != 0):
             continue
         if t == 0:

@@ -179,7 +179,9 @@ int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void
  * TN_C64_4M also 5 = 256x128 and 6 = 128x128 with raised matrix-core
  * priority; for TN_C64_4M and TN_C64_3M 7 = 128x128, 8 = 256x128 and
  * 9 = 128x128 at more waves per SIMD, all direct-to-LDS (operands whose
- * summed indices are their lowest axes); for TN_C64_BF16X3, on operands
+ * summed indices are their lowest axes), and for TN_C64_4M 14 = 128x128
+ * direct-to-LDS with the next stage's fragments read during the current
+ * stage's matrix-core work; for TN_C64_BF16X3, on operands
  * split into bf16 planes beforehand, all direct-to-LDS: 10 = 128x128,
  * 11 = 256x128 (the default), 12 = 128x128 with three stages in flight,
  * 13 = 256x128 with the next stage's fragments read during the current

@@ -36,7 +36,7 @@ int gemm_tile_bits(int tile, int* bm, int* bn);
 bool gemm_tile_ok(const GemmOp& op, int tile, int prec);
 // kernel (template instance) that launch_gemm runs for op's tile at precision prec
 const char* gemm_kernel_name(const GemmOp& op, int prec);
-constexpr int kNumGemmTiles = 14;
+constexpr int kNumGemmTiles = 15;
 constexpr int kSplitTile = 10;      // first BF16x3 variant on pre-split operands (direct-to-LDS)
 constexpr int kNumSplitTiles = 4;   // variants 10, 11, 12, 13
 constexpr int kNumTilesShared = 4;   // tiles 0..3 exist for every matrix-core kernel

@@ -433,10 +433,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 // hit disjoint banks.
 __device__ __forceinline__ int dl_unit(int r, int kp) { return r * 4 + (kp ^ ((r >> 2) & 3)); }
 
-template <int BM, int BN, int NW>
+template <int BM, int BN, int NW, int NB = 3>
 struct DlRing {
   static constexpr int IA = BM * 4 / 64 / NW, IB = BN * 4 / 64 / NW;   // load instructions per wave and stage
-  static constexpr int NBUF = 3;
+  static constexpr int NBUF = NB;
   static constexpr int UNITS = (BM + BN) * 4;                            // 16-byte units per buffer
   static_assert(IA >= 1 && IB >= 1, "tile too small");
   static_assert(IA * NW * 64 == BM * 4 && IB * NW * 64 == BN * 4, "tile / wave mismatch");
@@ -466,7 +466,9 @@ struct DlRing {
 
   // start the loads of stage `step` into its ring buffer
   __device__ __forceinline__ void issue(f4* lds, uint64_t step, int wave) const {
-    const int buf = (int)(step % NBUF);
+    issue_into(lds, step, (int)(step % NBUF), wave);
+  }
+  __device__ __forceinline__ void issue_into(f4* lds, uint64_t step, int buf, int wave) const {
     const uint32_t k0 = (uint32_t)(step << 3);
 #pragma unroll
     for (int i = 0; i < IA; i++)
@@ -489,6 +491,13 @@ struct DlRing {
   __device__ __forceinline__ static void wait(bool more) {
     if (more) __builtin_amdgcn_s_waitcnt((IA + IB) | (0x7 << 4) | (0xF << 8));
     else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
+    __builtin_amdgcn_s_barrier();
+  }
+  // the same with the loads of the `ahead` (constant) later stages still in flight
+  template <int AHEAD>
+  __device__ __forceinline__ static void wait_ahead() {
+    static_assert(AHEAD * (IA + IB) < 16, "wait counter field");
+    __builtin_amdgcn_s_waitcnt((AHEAD * (IA + IB)) | (0x7 << 4) | (0xF << 8));
     __builtin_amdgcn_s_barrier();
   }
 };
@@ -566,6 +575,100 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       }
     }
   }
+  __syncthreads();                         // the epilogue reuses the LDS ring for its tables
+  gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
+}
+
+// 4M on a ring of four stages with the next stage's fragments read during
+// the matrix-core work: at stage s the wave waits for stage s + 1's loads
+// (s + 2 stays in flight), passes the barrier (after which the buffer of
+// stage s - 1, whose fragments every wave read one stage earlier, is free),
+// starts the loads of stage s + 3 into it, and then issues stage s's
+// matrix-core ops block by block (k group q, column block j), reading stage
+// s + 1's B unit of a block into its registers right after the block's last
+// op and stage s + 1's A fragments of a k group after its last block.  Every
+// stage runs the same operations (past the last stage the loads fetch the
+// last stage again, into a buffer no later read uses, and the reads re-read
+// it), so the compiler's wait counts hold on every pass.  A's conjugation is
+// folded into the B entries it multiplies.
+template <int BM, int BN, int WGM, int WGN, int OCC>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void gemm_mfma_4m_dlp(Ctx ctx, GemmOp op) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN, NB = 4;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 16;
+  constexpr int RM = __builtin_ctz(BM), RN = __builtin_ctz(BN), RK = 3;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  typedef DlRing<BM, BN, NW, NB> Ring;
+  __shared__ __attribute__((aligned(16))) f4 lds[NB * Ring::UNITS];
+  static_assert(sizeof(lds) >= (BM + BN) * sizeof(uint64_t), "lds too small for epilogue tables");
+
+  GemmSetup g;
+  if (!gemm_setup(ctx, op, RM, RN, RK, g)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Ring ring(ctx, op, g, wave, lane);
+  const uint32_t nsteps = 1u << (op.n_k - RK);                 // a power of two (tensors hold < 2^32 elements)
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int hi = lane >> 5, c32 = lane & 31, p = c32 & 1;
+  const float sa = op.conj_a ? -1.f : 1.f, sb = op.conj_b ? -1.f : 1.f;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; i++)
+#pragma unroll
+    for (int j = 0; j < FN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  auto buf = [&](uint32_t s) { return &lds[(s & (NB - 1)) * Ring::UNITS]; };   // stage s's buffer
+  f4 fa[2][FM], fb[2][FN];                                     // raw LDS units, refilled as they die
+  auto read_a = [&](int q, uint32_t s) {
+    const f4* L = buf(s);
+#pragma unroll
+    for (int i = 0; i < FM; i++) fa[q][i] = L[dl_unit(wm * WM + i * 32 + c32, 2 * q + hi)];
+  };
+  auto read_b = [&](int q, int j, uint32_t s) {
+    fb[q][j] = buf(s)[BM * 4 + dl_unit(wn * WN + j * 16 + (c32 >> 1), 2 * q + hi)];
+  };
+  auto block = [&](int q, int j) {
+    const f4 u = fb[q][j];
+    const float br0 = u[0], bi0 = sb * u[1], br1 = u[2], bi1 = sb * u[3];
+    f4 v;
+    v[0] = p ? bi0 : br0;           // real k = re of the first complex k
+    v[1] = sa * (p ? br0 : -bi0);   // im of the first (A's imaginary part, conjugated when conj_a)
+    v[2] = p ? bi1 : br1;           // re of the second
+    v[3] = sa * (p ? br1 : -bi1);   // im of the second
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[q][i][e], v[e], acc[i][j], 0, 0, 0);
+  };
+  const uint32_t last = nsteps - 1;
+  auto clamp = [&](uint32_t t) { return t < last ? t : last; };
+  for (int q = 0; q < NB - 1; q++) ring.issue_into(lds, clamp((uint32_t)q), q, wave);
+  Ring::template wait_ahead<2>();                             // stage 0 loaded
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    read_a(q, 0);
+#pragma unroll
+    for (int j = 0; j < FN; j++) read_b(q, j, 0);
+  }
+  for (uint32_t s = 0; s < nsteps; s++) {
+    Ring::template wait_ahead<1>();                           // stage s + 1 loaded, s + 2 in flight
+    ring.issue_into(lds, clamp(s + 3), (s + 3) & (NB - 1), wave);
+    const uint32_t nx = clamp(s + 1);
+    // (scheduling barriers keep the compiler from reordering the blocks)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+      for (int j = 0; j < FN; j++) {
+        block(q, j);
+        read_b(q, j, nx);
+        if (j == FN - 1) read_a(q, nx);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+  Ring::template wait_ahead<0>();          // no load into the ring still in flight
   __syncthreads();                         // the epilogue reuses the LDS ring for its tables
   gemm_store<BM, BN, FM, FN>(ctx, op, g, reinterpret_cast<uint64_t*>(&lds[0]), acc, wm, wn, tid, NT);
 }
@@ -1560,6 +1663,7 @@ int gemm_tile_bits(int tile, int* bm, int* bn) {
     case 11: *bm = 8; *bn = 7; return 0;    // 256 x 128 BF16x3 on pre-split operands, 8 waves
     case 12: *bm = 7; *bn = 7; return 0;    // 128 x 128 BF16x3 on pre-split operands, 3 stages in flight
     case 13: *bm = 8; *bn = 7; return 0;    // 256 x 128 BF16x3 on pre-split operands, next stage's fragments prefetched
+    case 14: *bm = 7; *bn = 7; return 0;    // 128 x 128 direct-to-LDS 4M, 4-stage ring, next stage's fragments prefetched
     default: return -1;
   }
 }
@@ -1621,6 +1725,7 @@ const char* gemm_kernel_name(const GemmOp& op, int prec) {
     case 7: return "gemm_mfma_4m_dl<128,128,2,2>";
     case 8: return "gemm_mfma_4m_dl<256,128,4,2>";
     case 9: return "gemm_mfma_4m_dl<128,128,2,2,3>";
+    case 14: return "gemm_mfma_4m_dlp<128,128,2,2,2>";
     default: return "?";
   }
 }
@@ -1733,6 +1838,7 @@ static hipError_t launch_gemm_kernel(const Ctx& ctx, const GemmOp& op, int prec,
     case 7: hipLaunchKernelGGL((gemm_mfma_4m_dl<128, 128, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
     case 8: hipLaunchKernelGGL((gemm_mfma_4m_dl<256, 128, 4, 2>), grid, dim3(512), 0, s, ctx, op); break;
     case 9: hipLaunchKernelGGL((gemm_mfma_4m_dl<128, 128, 2, 2, 3>), grid, dim3(256), 0, s, ctx, op); break;
+    case 14: hipLaunchKernelGGL((gemm_mfma_4m_dlp<128, 128, 2, 2, 2>), grid, dim3(256), 0, s, ctx, op); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
