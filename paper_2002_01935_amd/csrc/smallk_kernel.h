@@ -7,6 +7,11 @@
 typedef float smallk_f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSmallkRows = 32;   // rows of the shared index per thread
+// log2 rows of the shared index per unit of the streaming variant (<= 5).
+// Measured on MI355X with 2^4 instead: (2^14, 2^14, 4) and (2^13, 2^13, 2) 3 %
+// and 8 % faster, (2^15, 2^15, 1) 1 % and (2^12, 2^12, 4) 9 % slower; with 2^3
+// (2^15, 2^15, 1) 16 % slower.
+constexpr int kStreamRowBits = 5;
 
 // Offsets the host computes once per launch: of summed value k in the
 // thread's own operand (kf) and in the shared one (ks); of row i < R of the
@@ -106,7 +111,8 @@ template <typename T, bool FASTN, int P, int KN>
 __global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, SmallkTables kt) {
   using V = typename C2<T>::t;
   static_assert(P == 1 || (P == 2 && sizeof(T) == 4), "paired stores are 16-byte complex64 pairs");
-  constexpr int R = kSmallkRows;
+  constexpr int R = 1 << kStreamRowBits;
+  static_assert(R <= kSmallkRows, "row offsets come from the launch tables");
   constexpr int LP = P == 2 ? 1 : 0;
   constexpr int Q = (R * KN + 63) / 64;   // shared-operand values per lane and unit
   const int nzh = ctx.n_batch;
@@ -117,7 +123,7 @@ __global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, Sm
   const int nf = FASTN ? op.n_n : op.n_m;
   const int ns = FASTN ? op.n_m : op.n_n;
   const int fbits = nf - LP - 6;                        // >= 0 (the launcher checks)
-  const uint32_t units = 1u << (fbits + ns - 5);        // R = 2^5 rows per unit
+  const uint32_t units = 1u << (fbits + ns - kStreamRowBits);
   const uint32_t lane = threadIdx.x & 63;
   // uniform over the wavefront (the compiler cannot tell by itself): the
   // unit offsets below are then scalar work
@@ -273,7 +279,7 @@ inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, 
   L.gy = uint64_t(n_batch) << op.n_h;
   L.kn = 1 << op.n_k;
   L.stream = !op.accumulate && nf - (L.pair ? 1 : 0) >= 6;
-  L.units = threads / 64;
+  L.units = (threads << (5 - kStreamRowBits)) / 64;          // units of 64 lanes x 2^kStreamRowBits rows
   return true;
 }
 
