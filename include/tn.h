@@ -164,10 +164,13 @@ int tn_plan_node_info(tn_plan_t plan, int32_t k, int32_t* kernel_class, int32_t*
  * of a shape fit about 6 s, else at the cut range; tn_plan_tune_trials
  * reports the table) and keeps the fastest in the plan, for the forward and the
  * backward program (contractions of the same shape, split and operand
- * layout class).  Without it, a contraction takes the direct-to-LDS variant
- * where its operands allow (tile 9 for TN_C64_4M, 7 for TN_C64_3M), else
- * tile 0.  Clears a tile pinned by tn_plan_set_tile.  Overwrites the
- * workspace; synchronises the stream.
+ * layout class); the default variant stays unless another is faster by more
+ * than 1 %, so that repeated runs execute the same kernels.  Without it, a
+ * contraction takes the default: the direct-to-LDS variant where its
+ * operands allow (tile 9 for TN_C64_4M, 7 for TN_C64_3M, 11 on pre-split
+ * BF16x3 operands), else tile 0 (10 on pre-split operands).  Clears a tile
+ * pinned by tn_plan_set_tile.  Overwrites the workspace; synchronises the
+ * stream.
  */
 int tn_plan_tune(tn_plan_t plan, void* workspace, uint64_t workspace_bytes, void* stream);
 
