@@ -115,7 +115,10 @@ typedef struct tn_plan_s* tn_plan_t;
  * Errors (TN_E_INVALID): null pointers; an index repeated within one leaf (a
  * self-loop); a non-output index on only one leaf; a tree that is not a full
  * binary tree over all leaves; a sliced index that is also an output, or
- * listed twice; an output listed twice.  Host-only: enqueues no GPU work.
+ * listed twice; an output listed twice.  TN_E_UNSUPPORTED: a tensor of the
+ * tree (leaf, intermediate or root) holds 2^32 or more elements once the
+ * sliced indices are removed (slice more indices).  Host-only: enqueues no
+ * GPU work.
  */
 int tn_plan(int32_t n_leaves, const int32_t* rank, const int64_t* leaf_idx,
             int32_t n_idx, const int64_t* idx_dim,

@@ -105,9 +105,14 @@ __global__ void counter_kernel(Ctx ctx, int64_t value, int add) {
   }
 }
 
+// Zeroes n_words 8-byte words: one per work-item up to 2^31 words (the
+// stores in flight then cover a narrow window of memory), grid-stride beyond
+// (a launch holds fewer than 2^32 work-items per grid dimension, and arenas
+// or complex128 outputs can hold more words than that).
 __global__ __launch_bounds__(256) void fill_kernel(uint64_t base, uint64_t n_words) {
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n_words) reinterpret_cast<uint64_t*>(base)[i] = 0;
+  const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_words; i += step)
+    reinterpret_cast<uint64_t*>(base)[i] = 0;
 }
 
 // ------------------------------------------------------------------ tile loaders
@@ -1887,7 +1892,9 @@ hipError_t launch_split(const Ctx& ctx, const SplitOp& in, hipStream_t s) {
 hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s) {
   const uint64_t words = (bytes + 7) / 8;
   if (words == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(words, 256)), dim3(256), 0, s, base, words);
+  const uint64_t blocks = blocks_for(words, 256);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)(blocks < (1u << 23) ? blocks : (1u << 23))), dim3(256), 0, s, base,
+                     words);
   return hipGetLastError();
 }
 

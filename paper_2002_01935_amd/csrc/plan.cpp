@@ -643,8 +643,10 @@ static int classes(tn_plan_s* p, std::string& err) {
       }
     for (int b : KR)
       if (!contains(KV, b) && !contains(KL, b)) { err = "internal: summed bit on one child only"; return TN_E_INVALID; }
-    if (KV.size() > 32 || KL.size() > 32 || KR.size() > 32) {
-      err = "a tensor has more than 2^32 elements after slicing (slice more indices)";
+    // 32-bit offsets in the bandwidth kernels, and at most 2^31 work-items
+    // in the launches that take one per element
+    if (KV.size() > 31 || KL.size() > 31 || KR.size() > 31) {
+      err = "a tensor has 2^32 or more elements after slicing (slice more indices)";
       return TN_E_UNSUPPORTED;
     }
     if (ni.K.size() > (size_t)kMaxBits || (ni.H.size() + std::max(ni.M.size(), ni.N.size())) > (size_t)kMaxBits ||

@@ -8,9 +8,11 @@
 // elements) and R indices of the other side: it loads its own K operand
 // values once and, per output, the other operand's K values, which all lanes
 // of a wavefront share (one cached address).  Without accumulation into C
-// and with a fast side of at least 64 threads the streaming variant runs
-// instead (persistent wavefronts, the next unit's operands loaded before the
-// current unit's stores).  The sum over k runs in index order in the storage
+// and with a fast side of at least 64 threads, a one-shot variant runs when
+// the fast side's operand fits the L2 (each wavefront writes a few
+// consecutive 1 KiB pieces of C), else the streaming variant (persistent
+// wavefronts, the next unit's operands loaded before the current unit's
+// stores).  The sum over k runs in index order in the storage
 // precision (FP32 for complex64, FP64 for complex128).
 #include <hip/hip_runtime.h>
 
@@ -39,12 +41,14 @@ hipError_t launch_gemm_smallk(const Ctx& ctx, const GemmOp& in, int prec, hipStr
   if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return hipErrorInvalidValue;
   if (L.blocks > 0x7fffffffULL || L.gy > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)L.blocks, (unsigned)L.gy, 1);
-  const dim3 sgrid(L.stream ? stream_grid_x(L.units, (unsigned)L.gy) : 1u, (unsigned)L.gy, 1);
-  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto stream) {
+  const dim3 sgrid(L.variant == kSmallkStream ? stream_grid_x(L.units, (unsigned)L.gy) : 1u, (unsigned)L.gy, 1);
+  const dim3 wgrid((unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1);   // units <= 2^31: at most 2^29 workgroups
+  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto variant) {
     using T = decltype(t);
     constexpr bool FN = decltype(fastn)::value;
-    constexpr int P = decltype(p)::value, KN = decltype(kn)::value;
-    if constexpr (decltype(stream)::value) gemm_smallk_stream<T, FN, P, KN><<<sgrid, 256, 0, s>>>(ctx, op, kt);
+    constexpr int P = decltype(p)::value, KN = decltype(kn)::value, VAR = decltype(variant)::value;
+    if constexpr (VAR == kSmallkWide) gemm_smallk_wide<T, FN, P, KN><<<wgrid, 256, 0, s>>>(ctx, op, kt);
+    else if constexpr (VAR == kSmallkStream) gemm_smallk_stream<T, FN, P, KN><<<sgrid, 256, 0, s>>>(ctx, op, kt);
     else gemm_smallk<T, FN, P, R, KN><<<grid, 256, 0, s>>>(ctx, op, kt);
   });
   return hipGetLastError();
@@ -55,7 +59,7 @@ const char* smallk_kernel_name(const GemmOp& in, int prec) {
   SmallkTables kt;
   SmallkLaunch L;
   if (!smallk_prepare(op, prec, 1, kt, L)) return "gemm_smallk";
-  return L.stream ? "gemm_smallk_stream" : "gemm_smallk";
+  return L.variant == kSmallkWide ? "gemm_smallk_wide" : (L.variant == kSmallkStream ? "gemm_smallk_stream" : "gemm_smallk");
 }
 
 }  // namespace tn

@@ -12,6 +12,22 @@ constexpr int kSmallkRows = 32;   // rows of the shared index per thread
 // and 8 % faster, (2^15, 2^15, 1) 1 % and (2^12, 2^12, 4) 9 % slower; with 2^3
 // (2^15, 2^15, 1) 16 % slower.
 constexpr int kStreamRowBits = 5;
+// One-shot variant (gemm_smallk_wide): log2 of the 64-lane pieces of one row
+// that a wavefront writes and of its rows, by summed-value count KN; the
+// largest fast-side operand (log2 bytes per batch index) it takes, so that
+// the operand every row re-reads stays in the L2; the fewest outputs (log2)
+// for which it runs.  Measured on MI355X (ms per launch, streaming variant /
+// one-shot; C = A B with N lowest in C): 2^15 x 2^15 from one summed value
+// 1.49-1.51 / 1.40-1.41; 2^15 x 2^14 from two 0.761 / 0.622; 2^13 x 2^13 from
+// two 0.109 / 0.090; 2^14 x 2^14 from four 0.418-0.421 / 0.361-0.370; 2^12 x
+// 2^12 from four 0.032 / 0.037 (below the output threshold).  Four pieces of
+// one row for KN = 1 beat two pieces (2.17 ms on the first node) and eight
+// (1.49); for KN = 4 one row of four pieces made 2^14 x 2^14 take 0.97 ms
+// (eight operand loads per store).
+constexpr int wide_piece_bits(int kn) { return kn == 1 ? 2 : (kn == 2 ? 0 : 1); }
+constexpr int wide_row_bits(int kn) { return kn == 1 ? 0 : 2; }
+constexpr int kWideOperandBits = 22;
+constexpr int kWideMinOutputBits = 25;
 
 // Offsets the host computes once per launch: of summed value k in the
 // thread's own operand (kf) and in the shared one (ks); of row i < R of the
@@ -224,6 +240,103 @@ __global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, Sm
   else run(std::false_type());
 }
 
+// One-shot variant for ops whose fast-side operand stays in the L2 (without
+// accumulation into C): each wavefront writes 2^wide_piece_bits(KN)
+// consecutive 64-lane pieces of the fast index for 2^wide_row_bits(KN) rows of
+// the shared index, after loading its own operand values (vector loads, L2
+// hits) and the rows' shared values (scalar loads), and ends.  Consecutive wavefronts take
+// consecutive pieces, and workgroups start in index order, so the stores in
+// flight over the whole chip stay within a narrow window of C; persistent
+// wavefronts (the streaming variant) drift apart and spread theirs, which
+// the HBM takes more slowly.
+template <typename T, bool FASTN, int P, int KN>
+__global__ __launch_bounds__(256) void gemm_smallk_wide(Ctx ctx, GemmOp op, SmallkTables kt) {
+  using V = typename C2<T>::t;
+  static_assert(P == 1 || (P == 2 && sizeof(T) == 4), "paired stores are 16-byte complex64 pairs");
+  constexpr int PB = wide_piece_bits(KN), RB = wide_row_bits(KN);
+  constexpr int TP = 1 << PB, RW = 1 << RB;
+  static_assert(RW <= kSmallkRows, "row offsets come from the launch tables");
+  constexpr int LP = P == 2 ? 1 : 0;
+  const int nzh = ctx.n_batch;
+  const int z = blockIdx.y % nzh;
+  const uint32_t h = blockIdx.y / nzh;
+  const int64_t sid = slice_id(ctx, z);
+  if (sid < 0) return;
+  const int nf = FASTN ? op.n_n : op.n_m;
+  const int ns = FASTN ? op.n_m : op.n_n;
+  const int gbits = nf - LP - 6 - PB;                   // >= 0 (the launcher checks)
+  const uint64_t units = uint64_t(1) << (gbits + ns - RB);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t u = TN_UNIFORM(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (u >= units) return;
+  const int eb = sizeof(V);
+  GMEM const V* A = reinterpret_cast<GMEM const V*>(resolve(ctx, op.a, z, sid, eb)) + deposit_runs32(h, op.run_a_h);
+  GMEM const V* B = reinterpret_cast<GMEM const V*>(resolve(ctx, op.b, z, sid, eb)) + deposit_runs32(h, op.run_b_h);
+  GMEM V* C = reinterpret_cast<GMEM V*>(resolve(ctx, op.c, z, sid, eb)) + deposit_runs32(h, op.run_c_h);
+  GMEM const V* F = FASTN ? B : A;
+  CMEM const V* S = reinterpret_cast<CMEM const V*>(reinterpret_cast<uintptr_t>(FASTN ? A : B));
+  const BitRuns& rf = FASTN ? op.run_b_n : op.run_a_m;
+  const BitRuns& rs = FASTN ? op.run_a_m : op.run_b_n;
+  const BitRuns& rcf = FASTN ? op.run_c_n : op.run_c_m;
+  const BitRuns& rcs = FASTN ? op.run_c_m : op.run_c_n;
+  const int cjf = FASTN ? op.conj_b : op.conj_a, cjs = FASTN ? op.conj_a : op.conj_b;
+  // pieces: fast index ((g TP + t) 64 + lane) 2^LP; rows r0 .. r0 + RW - 1
+  const uint32_t g = u & ((1u << gbits) - 1), r0 = (u >> gbits) << RB;
+  const uint32_t lf = deposit_runs32(lane << LP, rf), lcf = deposit_runs32(lane << LP, rcf);
+  V fv[TP][P][KN], sv[RW][KN];
+#pragma unroll
+  for (int t = 0; t < TP; t++) {
+    GMEM const V* Fp = F + deposit_runs_u(((g << PB) + t) << (6 + LP), rf) + lf;
+#pragma unroll
+    for (int p = 0; p < P; p++)
+#pragma unroll
+      for (int k = 0; k < KN; k++) fv[t][p][k] = conjv(ld(Fp + (p ? kt.f1 : 0u) + kt.kf[k]), cjf);
+  }
+  const uint32_t so = deposit_runs_u(r0, rs);
+#pragma unroll
+  for (int i = 0; i < RW; i++)
+#pragma unroll
+    for (int k = 0; k < KN; k++) sv[i][k] = conjv(ldc(S + so + kt.si[i] + kt.ks[k]), cjs);
+  const uint32_t co = deposit_runs_u(r0, rcs);
+  uint32_t cp[TP];
+#pragma unroll
+  for (int t = 0; t < TP; t++) cp[t] = deposit_runs_u(((g << PB) + t) << (6 + LP), rcf);
+  auto run = [&](auto aligned) {
+#pragma unroll
+    for (int i = 0; i < RW; i++)
+#pragma unroll
+      for (int t = 0; t < TP; t++) {
+        V acc[P];
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          acc[p].x = 0;
+          acc[p].y = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < KN; k++)
+#pragma unroll
+          for (int p = 0; p < P; p++)
+            acc[p] = FASTN ? cfma(acc[p], sv[i][k], fv[t][p][k]) : cfma(acc[p], fv[t][p][k], sv[i][k]);
+        GMEM V* d = C + co + kt.ci[i] + cp[t] + lcf;
+        if constexpr (P == 2) {
+          if constexpr (decltype(aligned)::value) {
+            smallk_f4 v = {acc[0].x, acc[0].y, acc[1].x, acc[1].y};
+            *reinterpret_cast<GMEM smallk_f4*>(d) = v;
+          } else {
+            st(d, acc[0]);
+            st(d + 1, acc[1]);
+          }
+        } else {
+          st(d, acc[0]);
+        }
+      }
+  };
+  // as in the streaming variant: 16-byte alignment of every paired store
+  // follows from C's own
+  if (P == 2 && (reinterpret_cast<uint64_t>(C) & 15) == 0) run(std::true_type());
+  else run(std::false_type());
+}
+
 // Offset of a small value v (its set bits among the first n of a position list).
 inline uint32_t deposit_small(uint32_t v, const int8_t* pos, int n) {
   uint32_t off = 0;
@@ -233,17 +346,28 @@ inline uint32_t deposit_small(uint32_t v, const int8_t* pos, int n) {
 }
 
 
+// Kernel variants of a launch.
+enum SmallkVariant { kSmallkPlain = 0, kSmallkStream = 1, kSmallkWide = 2 };
+
 // Grid and variant of one launch: units = wavefronts per grid row of the
-// streaming variant (stream), blocks = workgroups per grid row of the other.
+// streaming and one-shot variants, blocks = workgroups per grid row of the
+// plain one.
 struct SmallkLaunch {
-  bool fastn, pair, stream;
+  bool fastn, pair;
+  int variant;
   int kn;
   uint64_t blocks, gy, units;
 };
 
+// When the one-shot variant may run (smallk_prepare): never, by the rule
+// above, or whatever the output size (the last two for the host emulation's
+// tests on small operands).
+enum SmallkWideRule { kWideNever = 0, kWideDefault = 1, kWideAnySize = 2 };
+
 // Host side of a launch: the op's position lists as runs, the offset tables
 // and the grid.  False when the op does not qualify.
-inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, SmallkLaunch& L) {
+inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, SmallkLaunch& L,
+                           int wide_rule = kWideDefault) {
   constexpr int R = kSmallkRows;
   if (!gemm_smallk_ok(op)) return false;
   make_runs(op.a_h, op.n_h, op.run_a_h);
@@ -278,27 +402,41 @@ inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, 
   L.blocks = (threads + 255) / 256;
   L.gy = uint64_t(n_batch) << op.n_h;
   L.kn = 1 << op.n_k;
-  L.stream = !op.accumulate && nf - (L.pair ? 1 : 0) >= 6;
-  L.units = (threads << (5 - kStreamRowBits)) / 64;          // units of 64 lanes x 2^kStreamRowBits rows
+  const int lp = L.pair ? 1 : 0, eb = prec == TN_C128 ? 16 : 8;
+  const int kn = 1 << op.n_k, pb = wide_piece_bits(kn), rb = wide_row_bits(kn);
+  const int wide_bits = nf - lp - 6 - pb + ns - rb;         // log2 wavefronts per grid row
+  if (wide_rule != kWideNever && !op.accumulate && nf - lp >= 6 + pb && ns >= rb && wide_bits + 6 <= 31 &&
+      (nf + ns >= kWideMinOutputBits || wide_rule == kWideAnySize) &&
+      nf + op.n_k + __builtin_ctz(eb) <= kWideOperandBits) {
+    L.variant = kSmallkWide;
+    L.units = uint64_t(1) << wide_bits;
+  } else if (!op.accumulate && nf - lp >= 6) {
+    L.variant = kSmallkStream;
+    L.units = (threads << (5 - kStreamRowBits)) / 64;        // units of 64 lanes x 2^kStreamRowBits rows
+  } else {
+    L.variant = kSmallkPlain;
+    L.units = 0;
+  }
   return true;
 }
 
-// Calls f(T(), fastn, p, kn, stream) with the launch's variant as
+// Calls f(T(), fastn, p, kn, variant) with the launch's variant as
 // std::integral_constant / bool_constant values.
 template <class Fn>
 inline void smallk_dispatch(const SmallkLaunch& L, int prec, Fn&& f) {
-  auto with_kn = [&](auto t, auto fastn, auto p, auto stream) {
-    if (L.kn == 1) f(t, fastn, p, std::integral_constant<int, 1>(), stream);
-    else if (L.kn == 2) f(t, fastn, p, std::integral_constant<int, 2>(), stream);
-    else f(t, fastn, p, std::integral_constant<int, 4>(), stream);
+  auto with_kn = [&](auto t, auto fastn, auto p, auto variant) {
+    if (L.kn == 1) f(t, fastn, p, std::integral_constant<int, 1>(), variant);
+    else if (L.kn == 2) f(t, fastn, p, std::integral_constant<int, 2>(), variant);
+    else f(t, fastn, p, std::integral_constant<int, 4>(), variant);
   };
-  auto with_stream = [&](auto t, auto fastn, auto p) {
-    if (L.stream) with_kn(t, fastn, p, std::true_type());
-    else with_kn(t, fastn, p, std::false_type());
+  auto with_variant = [&](auto t, auto fastn, auto p) {
+    if (L.variant == kSmallkWide) with_kn(t, fastn, p, std::integral_constant<int, kSmallkWide>());
+    else if (L.variant == kSmallkStream) with_kn(t, fastn, p, std::integral_constant<int, kSmallkStream>());
+    else with_kn(t, fastn, p, std::integral_constant<int, kSmallkPlain>());
   };
   auto with_fastn = [&](auto t, auto p) {
-    if (L.fastn) with_stream(t, std::true_type(), p);
-    else with_stream(t, std::false_type(), p);
+    if (L.fastn) with_variant(t, std::true_type(), p);
+    else with_variant(t, std::false_type(), p);
   };
   if (prec == TN_C128) with_fastn(double(), std::integral_constant<int, 1>());
   else if (L.pair) with_fastn(float(), std::integral_constant<int, 2>());

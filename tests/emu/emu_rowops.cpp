@@ -10,7 +10,9 @@
 //   NET.txt: n_leaves n_idx n_out prec / ranks / leaf indices / dims / out / left / right /
 //            n_sliced sliced... / n_ids ids...
 //   LEAVES.bin: complex128 leaves, row-major; OUT.bin: complex128 roots (out order), one per id
-//   FLAGS: tn_options.flags of the plan (default 0)
+//   FLAGS: tn_options.flags of the plan (default 0), plus 0x10000: no one-shot
+//          few-summed-values variant (the streaming one runs instead), 0x20000:
+//          that variant whatever the output size
 // exit code 3: the plan holds an op kind the emulator does not run (matrix-core GEMM)
 // exit code 4: a few-summed-values GEMM op its launch preparation refused
 #include <algorithm>
@@ -195,6 +197,12 @@ static void run_row_stream(const Ctx& ctx, const RowOp& op, int z) {
 }
 
 static int g_stream_ops = 0;   // streaming launches run (reported on stderr)
+static int g_wide_ops = 0;     // one-shot few-summed-values launches run (reported on stderr)
+// FLAGS bits of the emulator itself (not plan flags): leave out the one-shot
+// few-summed-values variant, so that small test operands reach the streaming
+// one; or run it whatever the output size
+constexpr uint32_t kEmuNoWide = 0x10000, kEmuWideAnySize = 0x20000;
+static int g_wide_rule = kWideDefault;
 
 template <typename T>
 static void run_row(const Ctx& ctx, const RowOp& op, int z) {
@@ -275,21 +283,33 @@ static void run_reduce(const Ctx& ctx, const RowOp& op, int z) {
 }
 
 // One launch of the few-summed-values GEMM kernel, in the variant the
-// library's launcher picks: the plain kernel thread by thread (it has no
-// cross-lane step), the streaming one on one workgroup per grid row (four
-// persistent wavefronts walk all units).
+// library's launcher picks: the plain and one-shot kernels thread by thread
+// (they have no cross-lane step), the streaming one on one workgroup per grid
+// row (four persistent wavefronts walk all units).
 static bool run_smallk(const Ctx& ctx, const GemmOp& in, int prec) {
   GemmOp op = in;
   SmallkTables kt;
   SmallkLaunch L;
-  if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return false;
-  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto stream) {
+  if (!smallk_prepare(op, prec, ctx.n_batch, kt, L, g_wide_rule)) return false;
+  smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto variant) {
     using T = decltype(t);
     constexpr bool FN = decltype(fastn)::value;
-    constexpr int P = decltype(p)::value, KN = decltype(kn)::value;
-    if constexpr (decltype(stream)::value) {
+    constexpr int P = decltype(p)::value, KN = decltype(kn)::value, VAR = decltype(variant)::value;
+    if constexpr (VAR == kSmallkStream) {
       g_stream_ops++;
       run_waves(1, (unsigned)L.gy, [&] { gemm_smallk_stream<T, FN, P, KN>(ctx, op, kt); });
+    } else if constexpr (VAR == kSmallkWide) {
+      // no cross-lane step: thread by thread, over the launcher's grid
+      g_wide_ops++;
+      blockDim = {256, 1, 1};
+      gridDim = {(unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1};
+      for (uint64_t y = 0; y < L.gy; y++)
+        for (uint64_t x = 0; x < gridDim.x; x++)
+          for (unsigned th = 0; th < 256; th++) {
+            blockIdx = {(unsigned)x, (unsigned)y, 0};
+            threadIdx = {th, 0, 0};
+            gemm_smallk_wide<T, FN, P, KN>(ctx, op, kt);
+          }
     } else {
       blockDim = {256, 1, 1};
       gridDim = {(unsigned)L.blocks, (unsigned)L.gy, 1};
@@ -332,7 +352,9 @@ int main(int argc, char** argv) {
   for (int i = 0; i < nids; i++) { long x; fscanf(f, "%ld", &x); ids[i] = x; }
   fclose(f);
   p->opt.prec = (tn_precision)prec;
-  p->opt.flags = argc == 5 ? (uint32_t)strtoul(argv[4], nullptr, 0) : 0u;
+  const uint32_t flags = argc == 5 ? (uint32_t)strtoul(argv[4], nullptr, 0) : 0u;
+  g_wide_rule = (flags & kEmuNoWide) ? kWideNever : ((flags & kEmuWideAnySize) ? kWideAnySize : kWideDefault);
+  p->opt.flags = flags & ~(kEmuNoWide | kEmuWideAnySize);
   p->prec = p->opt.prec;
   p->elem_bytes = prec == TN_C128 ? 16 : 8;
   std::string err;
@@ -412,5 +434,6 @@ int main(int argc, char** argv) {
   fclose(fo);
   delete p;
   fprintf(stderr, "streaming launches: %d\n", g_stream_ops);
+  fprintf(stderr, "one-shot launches: %d\n", g_wide_ops);
   return 0;
 }

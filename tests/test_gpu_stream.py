@@ -1,10 +1,12 @@
-"""The streaming bandwidth kernels on the GPU (row_stream_kernel: no row bit
-in B, at most four summed values; gemm_smallk_stream: a GEMM with at most
-four summed values whose fast side spans a wavefront) at sizes where every
-persistent wavefront walks several units (a ragged last pass included),
-against the oracle: complex64 within 1e-5 of the exact value of the same
-complex64 leaves (normwise and max-componentwise), complex128 within 1e-10.
-Each case asserts that the node ran on the streaming kernel."""
+"""The bandwidth kernels of write-bound nodes on the GPU (row_stream_kernel:
+no row bit in B, at most four summed values; gemm_smallk_stream: a GEMM with
+at most four summed values whose fast side spans a wavefront, its operand
+larger than the L2; gemm_smallk_wide: the same with a small fast-side
+operand, one-shot) at sizes where every persistent wavefront walks several
+units (a ragged last pass included), against the oracle: complex64 within
+1e-5 of the exact value of the same complex64 leaves (normwise and
+max-componentwise), complex128 within 1e-10.  Each case asserts the kernel
+that ran."""
 
 import numpy as np
 import pytest
@@ -58,12 +60,37 @@ def test_row_stream_sliced(oracle_lib, prec):
     _run(net, prec, "row_stream_kernel", oracle_lib, sliced=[20])
 
 
-# (h, m, n, k): GEMM class by default (h + m + n + k >= 25), random axis orders
-SMALLK = [(0, 12, 12, 1), (0, 13, 12, 0), (1, 11, 11, 2), (0, 12, 13, 2), (2, 10, 12, 1)]
+# (h, m, n, k): GEMM class by default (h + m + n + k >= 25), random axis
+# orders; fast-side operands of at most 2^(13 + 2) values and at least 2^25
+# outputs per batch index: one-shot variant
+SMALLK = [(0, 13, 12, 0), (0, 12, 13, 2), (1, 13, 12, 1), (0, 13, 13, 1), (2, 12, 13, 2)]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])
 @pytest.mark.parametrize("shape", SMALLK)
-def test_smallk_stream(oracle_lib, shape, prec):
+def test_smallk_wide(oracle_lib, shape, prec):
+    net = pairwise_network(*shape, seed=7 * sum(shape) + 1, dims=(2,))
+    _run(net, prec, "gemm_smallk_wide", oracle_lib)
+
+
+# fewer outputs than the one-shot variant's threshold: streaming variant
+SMALLK_SMALL = [(0, 12, 12, 1), (1, 11, 11, 2), (2, 10, 12, 1)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK_SMALL)
+def test_smallk_stream_small(oracle_lib, shape, prec):
     net = pairwise_network(*shape, seed=7 * sum(shape) + 1, dims=(2,))
     _run(net, prec, "gemm_smallk_stream", oracle_lib)
+
+
+# (m, n, k) of A(M, K) x B(N, K) -> C(M, N) with N lowest in C: the fast side
+# N's operand holds 2^(n + k) >= 2^20 values (at least 8 MiB), more than the
+# one-shot variant takes, so the streaming variant runs
+SMALLK_BIG = [(6, 20, 0), (5, 19, 2), (7, 18, 2)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK_BIG)
+def test_smallk_stream(oracle_lib, shape, prec):
+    _run(_rows(*shape, seed=11 + sum(shape)), prec, "gemm_smallk_stream", oracle_lib)

@@ -37,12 +37,16 @@ def emu(tmp_path_factory):
     return out
 
 
-def run(emu, net, prec, sliced=(), ids=(0,), tmp=None, streams=None, gemm_all_sizes=False):
+def run(emu, net, prec, sliced=(), ids=(0,), tmp=None, streams=None, gemm_all_sizes=False, wides=None,
+        no_wide=False, wide_any_size=False):
     """Root values of the emulated plan; `streams`, a list, receives the
-    number of launches that took a streaming (persistent) kernel.
+    number of launches that took a streaming (persistent) kernel, `wides`
+    the number that took the one-shot few-summed-values kernel.
     gemm_all_sizes: GEMM-shaped contractions of any size take the GEMM class
     (the plan flag TN_FLAG_GEMM_ALL_SIZES), so that small test networks reach
-    the few-summed-values kernel."""
+    the few-summed-values kernel.  no_wide: that kernel's streaming variant
+    runs where the one-shot one would; wide_any_size: the one-shot variant
+    runs on outputs under its size threshold too."""
     d = tmp
     with open(os.path.join(d, "net.txt"), "w") as f:
         f.write(f"{net.n_leaves} {len(net.idx_dim)} {len(net.out_idx)} {PREC[prec]}\n")
@@ -57,14 +61,17 @@ def run(emu, net, prec, sliced=(), ids=(0,), tmp=None, streams=None, gemm_all_si
             np.ascontiguousarray(t, dtype=np.complex128).tofile(f)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     args = [emu, os.path.join(d, "net.txt"), os.path.join(d, "leaves.bin"), os.path.join(d, "out.bin")]
-    if gemm_all_sizes:
-        args.append("1")
+    flags = (1 if gemm_all_sizes else 0) | (0x10000 if no_wide else 0) | (0x20000 if wide_any_size else 0)
+    if flags:
+        args.append(str(flags))
     r = subprocess.run(args, capture_output=True, text=True, env=env)
     if r.returncode == 3:
         return None
     assert r.returncode == 0, r.stderr[-2000:]
     if streams is not None:
         streams.append(int(r.stderr.split("streaming launches:")[1].split()[0]))
+    if wides is not None:
+        wides.append(int(r.stderr.split("one-shot launches:")[1].split()[0]))
     return np.fromfile(os.path.join(d, "out.bin"), dtype=np.complex128)
 
 
@@ -178,9 +185,33 @@ def test_smallk_stream_emulated(emu, oracle_lib, tmp_path, shape, prec):
     for seed in range(3):
         net = pairwise_network(*shape, seed=4000 + 31 * seed + sum(shape), dims=(2,))
         streams = []
-        got = run(emu, net, prec, tmp=str(tmp_path), streams=streams, gemm_all_sizes=True)
+        got = run(emu, net, prec, tmp=str(tmp_path), streams=streams, gemm_all_sizes=True, no_wide=True)
         assert got is not None, "plan uses a matrix-core GEMM"
         n_stream += streams[0]
         ref = oracle_lib.contract(net, TWO).ravel()
         assert rel(got, ref) < TOL[prec], (shape, prec, seed)
     assert n_stream >= 1
+
+
+# (h, m, n, k): few-summed-values GEMMs whose fast side spans the one-shot
+# variant's pieces (small operands)
+SMALLK_WIDE = [(0, 9, 9, 2), (0, 10, 5, 1), (1, 9, 6, 0), (0, 5, 10, 2), (2, 9, 9, 1)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK_WIDE)
+def test_smallk_wide_emulated(emu, oracle_lib, tmp_path, shape, prec):
+    """gemm_smallk_wide on the host (below its output-size threshold): each
+    wavefront writes a few consecutive 64-lane pieces of one to four rows of
+    the shared index; random axis orders (either side fast, paired and single
+    stores), batch bits, one, two and four summed values."""
+    n_wide = 0
+    for seed in range(3):
+        net = pairwise_network(*shape, seed=5000 + 31 * seed + sum(shape), dims=(2,))
+        wides = []
+        got = run(emu, net, prec, tmp=str(tmp_path), wides=wides, gemm_all_sizes=True, wide_any_size=True)
+        assert got is not None, "plan uses a matrix-core GEMM"
+        n_wide += wides[0]
+        ref = oracle_lib.contract(net, TWO).ravel()
+        assert rel(got, ref) < TOL[prec], (shape, prec, seed)
+    assert n_wide >= 1

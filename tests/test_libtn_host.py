@@ -233,6 +233,13 @@ def test_size_limits(B):
     assert e.value.code == -2
     p = B.Plan(wide, two, sliced=[1, 2])
     assert p.info()["d_sliced"] == 4 and p.info()["W_s"] == 31
+    # exactly 2^32 elements: rejected too (launches with one work-item per
+    # element hold fewer than 2^32 per grid dimension)
+    at32 = Network([big((2,) * 32), big((2,) * 3)], [list(range(32)), [0, 1, 2]], [2] * 32, list(range(3, 32)))
+    with pytest.raises(B.TNError) as e:
+        B.Plan(at32, two)
+    assert e.value.code == -2
+    assert B.Plan(at32, two, sliced=[0]).info()["W_s"] == 31
 
 
 def test_degenerate_plans(B):
