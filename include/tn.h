@@ -272,6 +272,17 @@ int tn_contract_sliced_timed(tn_plan_t plan, const void* const* leaves, int64_t 
 int tn_plan_node_kernel(tn_plan_t plan, int32_t k, int32_t* tile, char* name, int32_t name_cap);
 
 /*
+ * Kernels of the contractions of the reverse program for the leaves
+ * wrt_leaf[0..n_wrt) (Sec. 2 pairwise products applied to cotangents), in
+ * program order, for reporting: *n receives their number; for i < min(*n,
+ * cap), names[i * name_cap ..] the i-th kernel's name as tn_plan_node_kernel
+ * writes it (NUL terminated, truncated if short).  Builds (and caches) the
+ * reverse program like tn_plan_backward_info.  names may be NULL.  Host-only.
+ */
+int tn_plan_backward_kernels(tn_plan_t plan, int32_t n_wrt, const int32_t* wrt_leaf, int32_t cap, int32_t* n,
+                             char* names, int32_t name_cap);
+
+/*
  * Trials of the last tn_plan_tune: *n receives their number; for i < min(*n,
  * cap): keys[6i .. 6i+5] the contraction shape (log2 H, M, N, K, split bits,
  * 1 if both operands hold the summed indices lowest), tiles[i] the variant,

@@ -30,7 +30,7 @@ EXPORTS = [
     "tn_plan_tune", "tn_contract", "tn_contract_sliced", "tn_contract_backward", "tn_plan_destroy",
     "tn_last_error", "tn_contract_sliced_timed", "tn_plan_set_tile", "tn_plan_node_kernel",
     "tn_plan_tune_trials", "tn_contract_sliced_noalloc", "tn_batch", "tn_batch_info", "tn_batch_prepare",
-    "tn_batch_contract", "tn_batch_destroy",
+    "tn_batch_contract", "tn_batch_destroy", "tn_plan_backward_kernels",
 ]
 OP_KINDS = {0: "row", 1: "splitk", 2: "reduce", 3: "gemm", 4: "accum", 5: "permute", 6: "counter", 7: "split"}
 
@@ -64,6 +64,7 @@ def _load():
     lib.tn_contract_backward.argtypes = [P, P, P, i32, P, P, i64, P, P, u64, P]
     lib.tn_contract_sliced_timed.argtypes = [P, P, i64, P, P, P, u64, P, i32, P, P, P, P, P, P]
     lib.tn_plan_node_kernel.argtypes = [P, i32, P, ctypes.c_char_p, i32]
+    lib.tn_plan_backward_kernels.argtypes = [P, i32, P, i32, P, ctypes.c_char_p, i32]
     lib.tn_plan_tune_trials.argtypes = [P, i32, P, P, P, P, P]
     lib.tn_contract_sliced_noalloc.argtypes = [P, P, i64, P, P, P]
     lib.tn_batch.argtypes = [i32, P, ctypes.POINTER(P)]
@@ -177,6 +178,18 @@ class Plan:
         ws, fl = ctypes.c_uint64(), ctypes.c_double()
         _check(lib.tn_plan_backward_info(self.handle, len(w), wp, ctypes.byref(ws), ctypes.byref(fl)))
         return dict(workspace_bytes=ws.value, flops_per_slice=fl.value)
+
+    def backward_kernels(self, wrt) -> list:
+        """Kernel names of the reverse program's contractions for leaves `wrt`,
+        in program order (tn_plan_backward_kernels)."""
+        w, wp = _arr(list(wrt), np.int32)
+        n = ctypes.c_int32()
+        _check(lib.tn_plan_backward_kernels(self.handle, len(w), wp, 0, ctypes.byref(n), None, 0))
+        cap, width = n.value, 96
+        buf = ctypes.create_string_buffer(max(cap, 1) * width)
+        _check(lib.tn_plan_backward_kernels(self.handle, len(w), wp, cap, ctypes.byref(n), buf, width))
+        raw = buf.raw
+        return [raw[i * width:(i + 1) * width].split(b"\0", 1)[0].decode() for i in range(min(cap, n.value))]
 
     def nodes(self) -> list:
         n = ctypes.c_int32()

@@ -252,6 +252,27 @@ extern "C" int tn_plan_node_kernel(tn_plan_t p, int32_t k, int32_t* tile, char* 
   return TN_OK;
 }
 
+extern "C" int tn_plan_backward_kernels(tn_plan_t p, int32_t n_wrt, const int32_t* wrt, int32_t cap, int32_t* n,
+                                        char* names, int32_t name_cap) {
+  if (!p || !n) return set_err(TN_E_INVALID, "null pointer");
+  PlanLock lk(p->mu);
+  int rc = ensure_backward(p, n_wrt, wrt);
+  if (rc) return rc;
+  int32_t i = 0;
+  for (const Op& op : p->bwd) {
+    if (op.kind != OpKind::Gemm && op.kind != OpKind::Row) continue;
+    if (names && name_cap > 0 && i < cap) {
+      int t = -1;
+      char* dst = names + (size_t)i * (size_t)name_cap;
+      std::strncpy(dst, op_kernel_name(p, op, &t), (size_t)name_cap - 1);
+      dst[name_cap - 1] = 0;
+    }
+    i++;
+  }
+  *n = i;
+  return TN_OK;
+}
+
 extern "C" int tn_plan_tune_trials(tn_plan_t p, int32_t cap, int32_t* n, int32_t* keys, int32_t* tiles,
                                    int32_t* k_bits, float* ms) {
   if (!p || !n) return set_err(TN_E_INVALID, "null pointer");

@@ -232,3 +232,33 @@ def test_backward_split_k(oracle_lib, prec):
     torch.cuda.synchronize()
     assert rel(g1, ref) < tol
     assert np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64_4m"])
+@pytest.mark.parametrize("shape", [(13, 2, 13), (14, 2, 12), (13, 1, 13)])
+def test_backward_one_shot_smallk(oracle_lib, shape, prec):
+    """A(M, K) x B(N, K) with a short free side N: the gradient of A sums only
+    N (two or four values) into 2^(m + k) = 2^26 outputs, which the one-shot
+    few-summed-values kernel writes from B read conjugated (its only
+    conjugated use: forward programs never conjugate)."""
+    import torch
+
+    from tn_inputs.network import Network, Tree
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    m, n, k = shape
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    rng = np.random.default_rng(sum(shape) + 5)
+    a = rng.normal(size=(2,) * (m + k)) + 1j * rng.normal(size=(2,) * (m + k))
+    b = rng.normal(size=(2,) * (n + k)) + 1j * rng.normal(size=(2,) * (n + k))
+    net = Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
+    plan = _plan(net, two, precision=prec)
+    kernels = plan.backward_kernels([0])
+    note("backward one-shot smallk", prec, shape, kernels)
+    assert "gemm_smallk_wide" in kernels
+    go = rng.normal(size=(2,) * (m + n)) + 1j * rng.normal(size=(2,) * (m + n))
+    rnet = net if prec == "c128" else c64_leaves(net)
+    ref = oracle_lib.grad(rnet, two, go, [0])
+    got = plan.backward(to_dev(net, prec), torch.from_numpy(go), [0])
+    torch.cuda.synchronize()
+    _per_leaf([g.cpu().numpy() for g in got], ref, TOL_C128 if prec == "c128" else TOL_C64,
+              "backward one-shot smallk " + prec)

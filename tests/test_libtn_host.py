@@ -252,3 +252,20 @@ def test_degenerate_plans(B):
     two = Tree(np.array([0], np.int32), np.array([1], np.int32))
     unit = Network([np.ones((2, 1)), np.ones((1, 2))], [[0, 1], [1, 2]], [2, 1, 2], [0, 2])
     assert [n["logK"] for n in B.Plan(unit, two).nodes()] == [0]
+
+
+def test_backward_kernels_report(B):
+    # A(M, K) x B(N, K) with two free values on B: the forward contraction is
+    # a split-K row op; the reverse program recomputes it, then forms the
+    # gradient of A (summing N only, 2^26 outputs) on the one-shot
+    # few-summed-values kernel and the gradient of B on split-K
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    z = lambda r: np.broadcast_to(np.zeros(1, np.complex64), (2,) * r)  # noqa: E731
+    m, n, k = 13, 1, 13
+    M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    p = B.Plan(Network([z(m + k), z(n + k)], [M + K, N + K], [2] * (m + n + k), M + N), two)
+    assert [nd["kernel"] for nd in p.nodes()] == ["splitk_kernel"]
+    assert p.backward_kernels([0]) == ["splitk_kernel", "gemm_smallk_wide"]
+    assert p.backward_kernels([0, 1]) == ["splitk_kernel", "gemm_smallk_wide", "splitk_kernel"]
+    with pytest.raises(B.TNError):
+        p.backward_kernels([2])
