@@ -242,13 +242,14 @@ __global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, Sm
 
 // One-shot variant for ops whose fast-side operand stays in the L2 (without
 // accumulation into C): each wavefront writes 2^wide_piece_bits(KN)
-// consecutive 64-lane pieces of the fast index for 2^wide_row_bits(KN) rows of
-// the shared index, after loading its own operand values (vector loads, L2
-// hits) and the rows' shared values (scalar loads), and ends.  Consecutive wavefronts take
-// consecutive pieces, and workgroups start in index order, so the stores in
-// flight over the whole chip stay within a narrow window of C; persistent
-// wavefronts (the streaming variant) drift apart and spread theirs, which
-// the HBM takes more slowly.
+// consecutive 64-lane pieces of the fast index for 2^wide_row_bits(KN) rows
+// of the shared index, after loading its own operand values (vector loads,
+// L2 hits) and the rows' shared values (scalar loads), and ends.  Consecutive
+// wavefronts take consecutive pieces, and workgroups start in index order, so
+// the stores in flight over the whole chip stay within a narrow window of C;
+// persistent wavefronts (the streaming variant) drift apart and spread
+// theirs, which the HBM takes more slowly.  The sum over k runs in index
+// order from zero, as in the other variants (the same bits whichever runs).
 template <typename T, bool FASTN, int P, int KN>
 __global__ __launch_bounds__(256) void gemm_smallk_wide(Ctx ctx, GemmOp op, SmallkTables kt) {
   using V = typename C2<T>::t;
