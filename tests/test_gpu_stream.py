@@ -30,11 +30,11 @@ def _rows(m, n, k, seed):
     return Network([a, b], [M + K, N + K], [2] * (m + n + k), M + N)
 
 
-def _run(net, prec, kernel, oracle_lib, sliced=()):
+def _run(net, prec, kernel, oracle_lib, sliced=(), inflight=0):
     from paper_2002_01935_amd.binding import Plan
-    plan = Plan(net, TWO, sliced=list(sliced), precision=prec)
+    plan = Plan(net, TWO, sliced=list(sliced), precision=prec, max_inflight_slices=inflight)
     names = [nd["kernel"] for nd in plan.nodes()]
-    note("stream", prec, kernel, names, "sliced", list(sliced))
+    note("stream", prec, kernel, names, "sliced", list(sliced), "in flight", inflight)
     assert names == [kernel], names
     ref = oracle_lib.contract(net if prec == "c128" else c64_leaves(net), TWO)
     got = gpu_sliced(net, TWO, sliced=list(sliced), precision=prec, plan=plan)
@@ -57,7 +57,7 @@ def test_row_stream_sliced(oracle_lib, prec):
     """A summed index sliced: several slices in flight on the grid's second
     dimension, each walked by the persistent wavefronts."""
     net = _rows(20, 2, 2, seed=5)
-    _run(net, prec, "row_stream_kernel", oracle_lib, sliced=[20])
+    _run(net, prec, "row_stream_kernel", oracle_lib, sliced=[20], inflight=2)
 
 
 # (h, m, n, k): GEMM class by default (h + m + n + k >= 25), random axis
@@ -94,3 +94,12 @@ SMALLK_BIG = [(6, 20, 0), (5, 19, 2), (7, 18, 2)]
 @pytest.mark.parametrize("shape", SMALLK_BIG)
 def test_smallk_stream(oracle_lib, shape, prec):
     _run(_rows(*shape, seed=11 + sum(shape)), prec, "gemm_smallk_stream", oracle_lib)
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+def test_smallk_wide_sliced(oracle_lib, prec):
+    """One of two summed indices sliced, both slices in flight on the grid's
+    second dimension: each slice is a (2^13, 2^13, 2) node on the one-shot
+    kernel, the slices' roots summed in FP64."""
+    net = _rows(13, 13, 2, seed=9)
+    _run(net, prec, "gemm_smallk_wide", oracle_lib, sliced=[14], inflight=2)
