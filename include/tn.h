@@ -148,7 +148,7 @@ int tn_plan_backward_info(tn_plan_t plan, int32_t n_wrt, const int32_t* wrt_leaf
 
 /* Number of internal nodes, and per-node details for reporting: kernel class
    (0 = vector ALU row kernel, 1 = vector ALU split-K, 2 = GEMM: on the matrix
-   cores, or, with at most two summed bits, on the write-bound vector ALU kernel,
+   cores, or, with at most three summed bits, on the write-bound vector ALU kernel,
    3 = matrix-core GEMM with its summed range split across the grid and the
    partial tiles summed in a fixed order),
    log2 of the batch (H), free-left (M), free-right (N) and summed (K) sizes,

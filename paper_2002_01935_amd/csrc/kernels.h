@@ -16,9 +16,10 @@ hipError_t launch_accum(const Ctx& ctx, const AccumOp& op, bool f64, hipStream_t
 hipError_t launch_counter(const Ctx& ctx, int64_t value, int add, hipStream_t s);
 hipError_t launch_fill(uint64_t base, uint64_t bytes, hipStream_t s);
 hipError_t launch_split(const Ctx& ctx, const SplitOp& op, hipStream_t s);
-// Workgroups (of 4 wavefronts) along x of a persistent launch that needs
-// `waves` wavefronts per grid row, with gy grid rows: about
-// kStreamWavesPerCU wavefronts per compute unit over the whole grid.
+// Workgroups (of 4 wavefronts) along x of a persistent launch of `kernel`
+// that needs `waves` wavefronts per grid row, with gy grid rows: about
+// kStreamWavesPerCU wavefronts per compute unit over the whole grid, fewer
+// when the kernel's registers let a compute unit hold fewer at once.
 constexpr int kStreamWavesPerCU = 16;
 // Streaming row kernel: blocks of 64 rows per unit (1 or 2), and the store
 // mode for contiguous complex64 output blocks (1: coalesced pieces, 2: LDS
@@ -29,7 +30,7 @@ constexpr int kStreamWavesPerCU = 16;
 // coalesced 3.45 / 3.29.
 constexpr int kRowStreamBlocks = 2;
 constexpr int kRowStreamMode(int nin) { return nin >= 8 ? 2 : 1; }
-unsigned stream_grid_x(uint64_t waves, unsigned gy);
+unsigned stream_grid_x(uint64_t waves, unsigned gy, const void* kernel);
 // log2 tile sizes of a gemm tile variant; -1 if unknown
 int gemm_tile_bits(int tile, int* bm, int* bn);
 // whether tile variant `tile` can run op at precision prec

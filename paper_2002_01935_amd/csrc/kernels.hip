@@ -25,8 +25,11 @@
 //   gemm_valu      tiled vector-ALU complex GEMM, used for complex128.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "kernels.h"
 
@@ -1526,7 +1529,7 @@ __global__ __launch_bounds__(256) void gemm_valu(Ctx ctx, GemmOp op) {
 
 static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
-unsigned stream_grid_x(uint64_t waves, unsigned gy) {
+unsigned stream_grid_x(uint64_t waves, unsigned gy, const void* kernel) {
   static std::atomic<int> cus[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
@@ -1535,7 +1538,23 @@ unsigned stream_grid_x(uint64_t waves, unsigned gy) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
     cus[dev].store(n, std::memory_order_relaxed);
   }
-  const uint64_t want = uint64_t(n) * kStreamWavesPerCU / 4;      // 4 wavefronts per workgroup
+  // workgroups of this kernel one compute unit holds at once (its register
+  // count decides): a persistent workgroup that has to wait for another to
+  // finish would walk all its units only afterwards
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> resident;
+  int per_cu = kStreamWavesPerCU / 4;                               // 4 wavefronts per workgroup
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = resident.find(kernel);
+    if (it == resident.end()) {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = per_cu;
+      it = resident.emplace(kernel, nb).first;
+    }
+    per_cu = std::min(per_cu, it->second);
+  }
+  const uint64_t want = uint64_t(n) * per_cu;
   const uint64_t per_y = want / gy > 0 ? want / gy : 1;
   const uint64_t need = (waves + 3) / 4;
   return (unsigned)(need < per_y ? need : per_y);
@@ -1569,13 +1588,18 @@ static void launch_row_stream_n(const Ctx& ctx, const RowOp& op, hipStream_t s) 
   const bool contiguous = op.stage_c && sizeof(T) == 4 && NIN >= 2;
   const int rb = op.n_rows >= 7 ? kRowStreamBlocks : 1;
   const uint64_t waves = (uint64_t(1) << (op.n_rows - 6)) / rb;
-  const dim3 grid(stream_grid_x(waves, (unsigned)ctx.n_batch), ctx.n_batch);
+  auto grid = [&](const void* k) { return dim3(stream_grid_x(waves, (unsigned)ctx.n_batch, k), ctx.n_batch); };
   auto go = [&](auto kn) {
     constexpr int KN = decltype(kn)::value;
     auto with_rb = [&](auto mode) {
       constexpr int M = decltype(mode)::value;
-      if (rb == 2) hipLaunchKernelGGL((row_stream_kernel<T, NIN, KN, M, 2>), grid, dim3(kRowThreads), 0, s, ctx, op, ko);
-      else hipLaunchKernelGGL((row_stream_kernel<T, NIN, KN, M, 1>), grid, dim3(kRowThreads), 0, s, ctx, op, ko);
+      if (rb == 2) {
+        auto k = row_stream_kernel<T, NIN, KN, M, 2>;
+        hipLaunchKernelGGL(k, grid((const void*)k), dim3(kRowThreads), 0, s, ctx, op, ko);
+      } else {
+        auto k = row_stream_kernel<T, NIN, KN, M, 1>;
+        hipLaunchKernelGGL(k, grid((const void*)k), dim3(kRowThreads), 0, s, ctx, op, ko);
+      }
     };
     if constexpr (sizeof(T) == 4 && NIN >= 2)
       if (contiguous) {

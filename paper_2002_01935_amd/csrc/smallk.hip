@@ -1,7 +1,9 @@
-// Complex GEMM with at most four summed values, C[h][m][n] = sum_k A[h][m][k] B[h][n][k]
-// (Sec. 2: a pairwise contraction whose shared indices span at most two bits).
-// Each output needs at most 4 complex multiply-adds per 8 or 16 bytes written,
-// so these contractions are bound by the HBM write of C, not by arithmetic:
+// Complex GEMM with at most eight summed values, C[h][m][n] = sum_k A[h][m][k] B[h][n][k]
+// (Sec. 2: a pairwise contraction whose shared indices span at most three
+// bits).  Each output needs at most 8 complex multiply-adds per 8 or 16 bytes
+// written, so these contractions are bound by the HBM write of C, not by
+// arithmetic (eight values take about 60 % of the vector ALU's FP32 rate at
+// 6 TB/s of output):
 // a tile through LDS and matrix cores would spend its time in the load ->
 // product -> store chain of each block.  Here every thread owns one index of
 // the free side that holds C's lowest bit (consecutive lanes write consecutive
@@ -41,14 +43,19 @@ hipError_t launch_gemm_smallk(const Ctx& ctx, const GemmOp& in, int prec, hipStr
   if (!smallk_prepare(op, prec, ctx.n_batch, kt, L)) return hipErrorInvalidValue;
   if (L.blocks > 0x7fffffffULL || L.gy > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)L.blocks, (unsigned)L.gy, 1);
-  const dim3 sgrid(L.variant == kSmallkStream ? stream_grid_x(L.units, (unsigned)L.gy) : 1u, (unsigned)L.gy, 1);
-  const dim3 wgrid((unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1);   // units <= 2^31: at most 2^29 workgroups
+  const dim3 wgrid((unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1);   // units <= 2^25: at most 2^23 workgroups
   smallk_dispatch(L, prec, [&](auto t, auto fastn, auto p, auto kn, auto variant) {
     using T = decltype(t);
     constexpr bool FN = decltype(fastn)::value;
     constexpr int P = decltype(p)::value, KN = decltype(kn)::value, VAR = decltype(variant)::value;
-    if constexpr (VAR == kSmallkWide) gemm_smallk_wide<T, FN, P, KN><<<wgrid, 256, 0, s>>>(ctx, op, kt);
-    else if constexpr (VAR == kSmallkStream) gemm_smallk_stream<T, FN, P, KN><<<sgrid, 256, 0, s>>>(ctx, op, kt);
+    if constexpr (VAR == kSmallkWide) {
+      if constexpr (KN <= kWideMaxSummed) gemm_smallk_wide<T, FN, P, KN><<<wgrid, 256, 0, s>>>(ctx, op, kt);
+    }
+    else if constexpr (VAR == kSmallkStream) {
+      auto k = gemm_smallk_stream<T, FN, P, KN>;
+      const dim3 sgrid(stream_grid_x(L.units, (unsigned)L.gy, (const void*)k), (unsigned)L.gy, 1);
+      k<<<sgrid, 256, 0, s>>>(ctx, op, kt);
+    }
     else gemm_smallk<T, FN, P, R, KN><<<grid, 256, 0, s>>>(ctx, op, kt);
   });
   return hipGetLastError();

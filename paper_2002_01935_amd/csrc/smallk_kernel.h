@@ -28,6 +28,12 @@ constexpr int wide_piece_bits(int kn) { return kn == 1 ? 2 : (kn == 2 ? 0 : 1); 
 constexpr int wide_row_bits(int kn) { return kn == 1 ? 0 : 2; }
 constexpr int kWideOperandBits = 22;
 constexpr int kWideMinOutputBits = 25;
+// Eight summed values stay on the streaming variant: one-shot wavefronts then
+// need eight operand loads per store or an LDS exchange of the shared values,
+// and both ran slower (2^15 x 2^15 from eight: streaming 1.63 ms; one-shot
+// with vector loads of the shared values 3.83 ms, through LDS 2.29 ms; the
+// matrix-core GEMM 2.03 ms).
+constexpr int kWideMaxSummed = 4;
 
 // Offsets the host computes once per launch: of summed value k in the
 // thread's own operand (kf) and in the shared one (ks); of row i < R of the
@@ -35,7 +41,7 @@ constexpr int kWideMinOutputBits = 25;
 // the thread's first row (a multiple of R, so the bit sets are disjoint);
 // of the thread's second own index (P = 2) in its operand (f1).
 struct SmallkTables {
-  uint32_t kf[4], ks[4], si[32], ci[32], f1;
+  uint32_t kf[8], ks[8], si[32], ci[32], f1;
   uint32_t dci[5];   // ci[i + 1] - ci[i] when i has t trailing ones (streaming variant)
 };
 
@@ -66,12 +72,11 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
   GMEM V* Cr = C + deposit_runs32(f, FASTN ? op.run_c_n : op.run_c_m) +
                deposit_runs32(uint32_t(s0), FASTN ? op.run_c_m : op.run_c_n);
   const int cjf = FASTN ? op.conj_b : op.conj_a, cjs = FASTN ? op.conj_a : op.conj_b;
-  V fv[P][4];
+  V fv[P][KN];
 #pragma unroll
   for (int p = 0; p < P; p++)
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (k < KN) fv[p][k] = conjv(ld(F + (p ? kt.f1 : 0u) + kt.kf[k]), cjf);
+    for (int k = 0; k < KN; k++) fv[p][k] = conjv(ld(F + (p ? kt.f1 : 0u) + kt.kf[k]), cjf);
 #pragma unroll
   for (int i = 0; i < R; i++) {
     V acc[P];
@@ -81,12 +86,11 @@ __global__ __launch_bounds__(256) void gemm_smallk(Ctx ctx, GemmOp op, SmallkTab
       acc[p].y = 0;
     }
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (k < KN) {
-        const V sv = conjv(ld(S + kt.si[i] + kt.ks[k]), cjs);
+    for (int k = 0; k < KN; k++) {
+      const V sv = conjv(ld(S + kt.si[i] + kt.ks[k]), cjs);
 #pragma unroll
-        for (int p = 0; p < P; p++) acc[p] = FASTN ? cfma(acc[p], sv, fv[p][k]) : cfma(acc[p], fv[p][k], sv);
-      }
+      for (int p = 0; p < P; p++) acc[p] = FASTN ? cfma(acc[p], sv, fv[p][k]) : cfma(acc[p], fv[p][k], sv);
+    }
     GMEM V* d = Cr + kt.ci[i];
     if (op.accumulate) {
 #pragma unroll
@@ -163,7 +167,11 @@ __global__ __launch_bounds__(256) void gemm_smallk_stream(Ctx ctx, GemmOp op, Sm
 #pragma unroll
   for (int q = 0; q < Q; q++) {
     const uint32_t k = ((lane + 64 * q) / R) % KN;
-    ksl[q] = k == 0 ? kt.ks[0] : (k == 1 ? kt.ks[1] : (k == 2 ? kt.ks[2] : kt.ks[3]));
+    // selects over the table (no lane-dependent index into the kernel's arguments)
+    uint32_t v = kt.ks[0];
+#pragma unroll
+    for (int j = 1; j < KN; j++) v = k == uint32_t(j) ? kt.ks[j] : v;
+    ksl[q] = v;
   }
   // offsets split into the unit's part (uniform) and the lane's part: the
   // lane's fast-side index bits, and the shared row its loads cover
@@ -406,7 +414,8 @@ inline bool smallk_prepare(GemmOp& op, int prec, int n_batch, SmallkTables& kt, 
   const int lp = L.pair ? 1 : 0, eb = prec == TN_C128 ? 16 : 8;
   const int kn = 1 << op.n_k, pb = wide_piece_bits(kn), rb = wide_row_bits(kn);
   const int wide_bits = nf - lp - 6 - pb + ns - rb;         // log2 wavefronts per grid row
-  if (wide_rule != kWideNever && !op.accumulate && nf - lp >= 6 + pb && ns >= rb && wide_bits + 6 <= 31 &&
+  if (wide_rule != kWideNever && kn <= kWideMaxSummed && !op.accumulate && nf - lp >= 6 + pb && ns >= rb &&
+      wide_bits + 6 <= 31 &&
       (nf + ns >= kWideMinOutputBits || wide_rule == kWideAnySize) &&
       nf + op.n_k + __builtin_ctz(eb) <= kWideOperandBits) {
     L.variant = kSmallkWide;
@@ -428,7 +437,8 @@ inline void smallk_dispatch(const SmallkLaunch& L, int prec, Fn&& f) {
   auto with_kn = [&](auto t, auto fastn, auto p, auto variant) {
     if (L.kn == 1) f(t, fastn, p, std::integral_constant<int, 1>(), variant);
     else if (L.kn == 2) f(t, fastn, p, std::integral_constant<int, 2>(), variant);
-    else f(t, fastn, p, std::integral_constant<int, 4>(), variant);
+    else if (L.kn == 4) f(t, fastn, p, std::integral_constant<int, 4>(), variant);
+    else f(t, fastn, p, std::integral_constant<int, 8>(), variant);
   };
   auto with_variant = [&](auto t, auto fastn, auto p) {
     if (L.variant == kSmallkWide) with_kn(t, fastn, p, std::integral_constant<int, kSmallkWide>());

@@ -6,10 +6,10 @@
 namespace tn {
 
 // Whether a GEMM-class contraction takes the few-summed-values kernel: at most
-// two summed bits (K <= 4 values), no split over the summed range, and at
+// three summed bits (K <= 8 values), no split over the summed range, and at
 // least 2^5 values on each free side.
 inline bool gemm_smallk_ok(const GemmOp& op) {
-  return op.n_k <= 2 && op.k_split_bits <= 0 && op.n_m >= 5 && op.n_n >= 5 && op.n_m + op.n_n <= 40;
+  return op.n_k <= 3 && op.k_split_bits <= 0 && op.n_m >= 5 && op.n_n >= 5 && op.n_m + op.n_n <= 40;
 }
 
 }  // namespace tn

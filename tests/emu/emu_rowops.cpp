@@ -300,16 +300,18 @@ static bool run_smallk(const Ctx& ctx, const GemmOp& in, int prec) {
       run_waves(1, (unsigned)L.gy, [&] { gemm_smallk_stream<T, FN, P, KN>(ctx, op, kt); });
     } else if constexpr (VAR == kSmallkWide) {
       // no cross-lane step: thread by thread, over the launcher's grid
-      g_wide_ops++;
-      blockDim = {256, 1, 1};
-      gridDim = {(unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1};
-      for (uint64_t y = 0; y < L.gy; y++)
-        for (uint64_t x = 0; x < gridDim.x; x++)
-          for (unsigned th = 0; th < 256; th++) {
-            blockIdx = {(unsigned)x, (unsigned)y, 0};
-            threadIdx = {th, 0, 0};
-            gemm_smallk_wide<T, FN, P, KN>(ctx, op, kt);
-          }
+      if constexpr (KN <= kWideMaxSummed) {
+        g_wide_ops++;
+        blockDim = {256, 1, 1};
+        gridDim = {(unsigned)((L.units + 3) / 4), (unsigned)L.gy, 1};
+        for (uint64_t y = 0; y < L.gy; y++)
+          for (uint64_t x = 0; x < gridDim.x; x++)
+            for (unsigned th = 0; th < 256; th++) {
+              blockIdx = {(unsigned)x, (unsigned)y, 0};
+              threadIdx = {th, 0, 0};
+              gemm_smallk_wide<T, FN, P, KN>(ctx, op, kt);
+            }
+      }
     } else {
       blockDim = {256, 1, 1};
       gridDim = {(unsigned)L.blocks, (unsigned)L.gy, 1};

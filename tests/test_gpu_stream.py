@@ -74,7 +74,7 @@ def test_smallk_wide(oracle_lib, shape, prec):
 
 
 # fewer outputs than the one-shot variant's threshold: streaming variant
-SMALLK_SMALL = [(0, 12, 12, 1), (1, 11, 11, 2), (2, 10, 12, 1)]
+SMALLK_SMALL = [(0, 12, 12, 1), (1, 11, 11, 2), (2, 10, 12, 1), (0, 12, 12, 3)]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])
@@ -84,10 +84,22 @@ def test_smallk_stream_small(oracle_lib, shape, prec):
     _run(net, prec, "gemm_smallk_stream", oracle_lib)
 
 
+# eight summed values (the streaming variant whatever the operand size)
+SMALLK_EIGHT = [(0, 13, 12, 3), (1, 12, 13, 3), (2, 11, 12, 3)]
+
+
+@pytest.mark.parametrize("prec", ["c64_4m", "c128"])
+@pytest.mark.parametrize("shape", SMALLK_EIGHT)
+def test_smallk_stream_eight(oracle_lib, shape, prec):
+    net = pairwise_network(*shape, seed=7 * sum(shape) + 3, dims=(2,))
+    _run(net, prec, "gemm_smallk_stream", oracle_lib)
+
+
 # (m, n, k) of A(M, K) x B(N, K) -> C(M, N) with N lowest in C: the fast side
 # N's operand holds 2^(n + k) >= 2^20 values (at least 8 MiB), more than the
-# one-shot variant takes, so the streaming variant runs
-SMALLK_BIG = [(6, 20, 0), (5, 19, 2), (7, 18, 2)]
+# one-shot variant takes, so the streaming variant runs (one to eight summed
+# values)
+SMALLK_BIG = [(6, 20, 0), (5, 19, 2), (7, 18, 2), (6, 18, 3)]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])

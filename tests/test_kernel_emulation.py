@@ -98,9 +98,9 @@ def test_pairwise_emulated(emu, oracle_lib, tmp_path, shape, prec):
         assert rel(got, ref) < TOL[prec], (shape, prec, seed)
 
 
-# (h, m, n, k): GEMM-class contractions with at most two summed bits (outer
+# (h, m, n, k): GEMM-class contractions with at most three summed bits (outer
 # products included), which take the few-summed-values kernel
-SMALLK = [(0, 5, 5, 1), (2, 6, 5, 2), (1, 5, 7, 0), (0, 7, 5, 2), (3, 5, 5, 1), (0, 6, 6, 0)]
+SMALLK = [(0, 5, 5, 1), (2, 6, 5, 2), (1, 5, 7, 0), (0, 7, 5, 2), (3, 5, 5, 1), (0, 6, 6, 0), (0, 5, 6, 3), (1, 5, 5, 3)]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])
@@ -172,7 +172,7 @@ def test_stream_rows_emulated(emu, oracle_lib, tmp_path, shape):
 
 # (h, m, n, k): few-summed-values GEMMs whose fast side spans a wavefront,
 # which take the streaming variant
-SMALLK_STREAM = [(0, 8, 7, 2), (0, 7, 9, 0), (1, 8, 6, 1), (2, 7, 7, 2), (0, 9, 5, 1)]
+SMALLK_STREAM = [(0, 8, 7, 2), (0, 7, 9, 0), (1, 8, 6, 1), (2, 7, 7, 2), (0, 9, 5, 1), (0, 8, 7, 3)]
 
 
 @pytest.mark.parametrize("prec", ["c64_4m", "c128"])

@@ -269,3 +269,18 @@ def test_backward_kernels_report(B):
     assert p.backward_kernels([0, 1]) == ["splitk_kernel", "gemm_smallk_wide", "splitk_kernel"]
     with pytest.raises(B.TNError):
         p.backward_kernels([2])
+
+
+def test_eight_summed_values_take_smallk(B):
+    # a GEMM-class contraction with at most eight summed values runs on the
+    # few-summed-values kernels in every single precision (its products are
+    # plain FP32 there), never on the matrix cores; nine or more do
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    z = lambda r: np.broadcast_to(np.zeros(1, np.complex64), (2,) * r)  # noqa: E731
+    for k, prefix in ((3, "gemm_smallk"), (4, "gemm_mfma")):
+        m, n = 12, 13
+        M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+        net = Network([z(m + k), z(n + k)], [M + K, N + K], [2] * (m + n + k), M + N)
+        for prec in ("c64_4m", "c64_3m", "c64_bf16x3"):
+            kern = B.Plan(net, two, precision=prec).nodes()[0]["kernel"]
+            assert kern.startswith(prefix), (k, prec, kern)
