@@ -17,8 +17,8 @@ TWO = Tree(np.array([0], np.int32), np.array([1], np.int32))
 
 # (h, m, n, k) log2 class sizes: dot, outer, row kernel both orientations,
 # split-K with and without chunks, matrix-core GEMM (partial and full tiles,
-# K = 0, batch), the few-summed-values GEMM (one or two summed bits, with and
-# without batches), and tiny cases
+# K = 0, batch), the few-summed-values GEMM (one to three summed bits, with
+# and without batches), and tiny cases
 SHAPES = [(0, 0, 0, 0), (0, 0, 0, 10), (0, 3, 2, 0), (0, 10, 2, 3), (0, 2, 10, 3), (0, 1, 1, 16),
           (0, 4, 4, 8), (3, 2, 2, 2), (0, 5, 5, 0), (0, 6, 6, 4), (0, 7, 9, 5), (0, 10, 10, 8),
           (2, 6, 6, 3), (0, 12, 5, 1), (0, 8, 7, 11), (1, 9, 3, 6), (0, 5, 8, 2),

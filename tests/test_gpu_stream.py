@@ -1,8 +1,9 @@
 """The bandwidth kernels of write-bound nodes on the GPU (row_stream_kernel:
 no row bit in B, at most four summed values; gemm_smallk_stream: a GEMM with
-at most four summed values whose fast side spans a wavefront, its operand
-larger than the L2; gemm_smallk_wide: the same with a small fast-side
-operand, one-shot) at sizes where every persistent wavefront walks several
+at most eight summed values whose fast side spans a wavefront, with eight
+summed values, an operand larger than the L2 or fewer than 2^25 outputs;
+gemm_smallk_wide: the same with at most four summed values and a small
+fast-side operand, one-shot) at sizes where every persistent wavefront walks several
 units (a ragged last pass included), against the oracle: complex64 within
 1e-5 of the exact value of the same complex64 leaves (normwise and
 max-componentwise), complex128 within 1e-10.  Each case asserts the kernel
