@@ -284,3 +284,25 @@ def test_eight_summed_values_take_smallk(B):
         for prec in ("c64_4m", "c64_3m", "c64_bf16x3"):
             kern = B.Plan(net, two, precision=prec).nodes()[0]["kernel"]
             assert kern.startswith(prefix), (k, prec, kern)
+
+
+def test_smallk_variant_rules(B):
+    # which few-summed-values variant a node takes (host-side launch
+    # preparation, reported by tn_plan_node_kernel): the one-shot kernel for
+    # at most four summed values, at least 2^25 outputs and a fast-side
+    # operand (N here: lowest in C) of at most 4 MiB; else the streaming one
+    two = Tree(np.array([0], np.int32), np.array([1], np.int32))
+    z = lambda r: np.broadcast_to(np.zeros(1, np.complex64), (2,) * r)  # noqa: E731
+
+    def kernel(m, n, k, prec="c64_4m"):
+        M, K, N = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+        net = Network([z(m + k), z(n + k)], [M + K, N + K], [2] * (m + n + k), M + N)
+        return B.Plan(net, two, precision=prec).nodes()[0]["kernel"]
+
+    assert kernel(12, 13, 2) == "gemm_smallk_wide"          # 2^25 outputs
+    assert kernel(12, 12, 2) == "gemm_smallk_stream"        # 2^24 outputs
+    assert kernel(6, 19, 0) == "gemm_smallk_wide"           # fast operand 2^19 x 8 B = 4 MiB
+    assert kernel(6, 20, 0) == "gemm_smallk_stream"         # 8 MiB
+    assert kernel(6, 19, 0, "c128") == "gemm_smallk_stream"  # 2^19 x 16 B = 8 MiB
+    assert kernel(13, 12, 3) == "gemm_smallk_stream"        # eight summed values
+    assert kernel(13, 12, 2, "c64_bf16x3") == "gemm_smallk_wide"
