@@ -568,8 +568,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="c64_4m", choices=sorted(PEAK))
-    ap.add_argument("--slices-per-step", type=int, default=2)
-    ap.add_argument("--inflight", type=int, default=1, help="slices contracted together per graph replay")
+    ap.add_argument("--slices-per-step", type=int, default=None, help="default 2 (cfg3: 64)")
+    ap.add_argument("--inflight", type=int, default=None,
+                    help="slices contracted together per graph replay; default 1 (cfg3: 8)")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the other precisions")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -577,6 +578,11 @@ def main():
     ap.add_argument("--no-timed-pass", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the cfg4 forward + backward timing")
     args = ap.parse_args()
+    # cfg3's slices are small (about 26 ms each): eight share each graph
+    # replay, so that its ~1100 launches per replay are spread over them
+    spd, infl = {"cfg3": (64, 8)}.get(args.workload, (2, 1))
+    args.slices_per_step = spd if args.slices_per_step is None else args.slices_per_step
+    args.inflight = infl if args.inflight is None else args.inflight
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sliced contraction is measured on a single MI355X "
               "(slices would shard across GPUs with one all-reduce of the result; not built here)",
