@@ -1,6 +1,8 @@
-"""Full-size parity in the launch configuration bench.py times (one in-flight
-slice, autotuned tiles, graph replay): a whole slice of cfg5 and cfg5h
-(width 30) and of cfg3 (width 27) runs on the GPU with a few more indices
+"""Full-size parity in the launch configuration bench.py times (autotuned
+tiles, graph replay, one in-flight slice; bench.py replays cfg3's slices
+eight at a time, and results do not depend on the number in flight:
+tests/test_gpu_parity.py test_sliced_subsets_and_batches): a whole slice of
+cfg5 and cfg5h (width 30) and of cfg3 (width 27) runs on the GPU with a few more indices
 projected out of the leaves (tests/gpu_util.project), and the oracle
 evaluates the matching sub-slice of the same tree on the same complex64
 leaves.
