@@ -599,7 +599,9 @@ def main():
     net, tree, sliced = configs.load(args.workload)
     plan = Plan(net, tree, sliced=sliced, precision=args.precision, max_inflight_slices=args.inflight)
     info = plan.info()
-    ids_all = configs.slice_subset(info["d_sliced"], seed=0, size=256)
+    # seeded distinct slice ids: 256, or as many as the run contracts
+    ids_all = configs.slice_subset(info["d_sliced"], seed=0,
+                                   size=max(256, args.slices_per_step * (args.steps + args.warmup)))
     B = max(1, min(args.slices_per_step, len(ids_all)))
     log(f"workload {args.workload}: W={info['W']} W_s={info['W_s']} d_sliced={info['d_sliced']} "
         f"8C/slice={info['flops_per_slice']:.3e} workspace={info['workspace_bytes'] / 2**30:.1f} GiB")
