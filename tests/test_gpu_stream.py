@@ -116,3 +116,20 @@ def test_smallk_wide_sliced(oracle_lib, prec):
     kernel, the slices' roots summed in FP64."""
     net = _rows(13, 13, 2, seed=9)
     _run(net, prec, "gemm_smallk_wide", oracle_lib, sliced=[14], inflight=2)
+
+
+@pytest.mark.parametrize("prec", ["c64_3m", "c64_bf16x3"])
+@pytest.mark.parametrize("shape,kernel", [((0, 13, 12, 1), "gemm_smallk_wide"), ((0, 13, 12, 3), "gemm_smallk_stream")])
+def test_smallk_other_precisions(oracle_lib, shape, kernel, prec):
+    """3M and BF16x3 plans send the same nodes to the few-summed-values
+    kernels, which form plain FP32 products there: held to the complex64
+    bound, not to the looser bounds of those precisions' GEMMs."""
+    from paper_2002_01935_amd.binding import Plan
+    net = pairwise_network(*shape, seed=7 * sum(shape) + 5, dims=(2,))
+    plan = Plan(net, TWO, precision=prec)
+    names = [nd["kernel"] for nd in plan.nodes()]
+    note("smallk", prec, shape, names)
+    assert names == [kernel], names
+    ref = oracle_lib.contract(c64_leaves(net), TWO)
+    got = gpu_sliced(net, TWO, precision=prec, plan=plan)
+    check(got.ravel(), ref.ravel(), TOL_C64, "smallk", prec, kernel)
